@@ -1,0 +1,111 @@
+/*
+ * RACIPE CPU oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, FP64 reference for what the GPU path computes.  Only the
+ * test suite, the smoke check and the benchmark's CPU-baseline leg may load
+ * it.  It shares no code, header, table or helper with the GPU library.
+ *
+ * What it implements (GRiNS paper, arXiv 2503.18356):
+ *   - the RACIPE node ODE (Eq. 1) with the shifted Hill function (Eq. 2),
+ *     evaluated literally with pow();
+ *   - parameter and initial-condition sampling with the default ranges of
+ *     Table 1, the inverted inhibitory fold change (Sec. 2.1.2) and the
+ *     threshold window 0.02..1.98 x median of the source's G/k (Sec. 2.1.2,
+ *     simplified to the prior median of G/k);
+ *   - an adaptive Dormand-Prince 5(4) integrator run to a steady state or to
+ *     a list of output times (Sec. 2.1.3), fixed-step RK4 and fixed-step DP5
+ *     for cross-checks;
+ *   - Philox4x64-10 (Salmon et al., SC'11) as the counter-based generator.
+ *
+ * Parameter layout is set-index fastest: G[i*P + p], T[e*P + p], ...
+ * Edges are in canonical order, sorted by (dst, src).
+ */
+#ifndef RACIPE_ORACLE_H
+#define RACIPE_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Philox4x64 with 10 rounds. */
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+/* Sort an edge list into canonical (dst, src) order.  Returns 0, or -1 on a
+ * bad index / duplicate edge / bad sign. */
+int orc_canonicalize(int n_genes, int n_edges, const int32_t* src, const int32_t* dst,
+                     const int8_t* sign, int32_t* out_src, int32_t* out_dst, int8_t* out_sign);
+
+/* Sampling ranges; values <= 0 in t_median ask for the prior median of G/k. */
+typedef struct {
+    double g_min, g_max, k_min, k_max;
+    double lam_act_min, lam_act_max, lam_inh_min, lam_inh_max;
+    int32_t n_min, n_max;
+    double t_lo, t_hi, t_median;
+} orc_ranges;
+
+void orc_default_ranges(orc_ranges* r);
+double orc_gk_median(const orc_ranges* r);
+
+/* Sample sets [set_begin, set_begin+n_sets) into arrays of stride n_sets, and
+ * n_ic initial-condition fractions ic[c*N + i] (ic may be NULL). */
+int orc_sample(int n_genes, int n_edges, const int8_t* sign_canon, const orc_ranges* r,
+               uint64_t seed, int64_t set_begin, int64_t n_sets, int32_t n_ic,
+               float* G, float* k, float* T, float* lam, uint8_t* n, float* ic);
+
+typedef struct {
+    double t0, t_end, rtol, atol, ss_atol, ss_rtol, h0;
+    int64_t max_steps;
+    int32_t divide_act_by_lambda; /* 1 = Eq. 1 as printed */
+    int32_t stop_at_steady;       /* time-series mode only */
+    int32_t ic_absolute;          /* ic holds absolute values, not fractions of G/k */
+} orc_opts;
+
+void orc_default_opts(orc_opts* o);
+
+/* A network with its parameters.  src/dst/sign are canonical. */
+typedef struct {
+    int32_t n_genes, n_edges;
+    const int32_t* src;
+    const int32_t* dst;
+    const int8_t* sign;
+    const float* G;
+    const float* k;
+    const float* T;
+    const float* lam;
+    const uint8_t* n;
+    int64_t n_sets; /* stride of the parameter arrays */
+    const float* ic;
+    int32_t n_ic;
+} orc_problem;
+
+enum { ORC_CONVERGED = 0, ORC_T_END = 1, ORC_MAX_STEPS = 2, ORC_STEP_UNDERFLOW = 3, ORC_NONFINITE = 4 };
+
+/* Right-hand side of Eq. 1 for parameter set p at state x. */
+void orc_rhs(const orc_problem* pb, int64_t p, int32_t divide, const double* x, double* f);
+
+/* Steady-state solve of the trajectories traj_ids[0..n_traj) (traj = p*n_ic + c);
+ * traj_ids NULL means all P*n_ic.  x_out[n_traj][N]. */
+int orc_steady_states(const orc_problem* pb, const orc_opts* o, const int64_t* traj_ids,
+                      int64_t n_traj, int32_t n_threads, double* x_out, double* t_final,
+                      int8_t* status, int32_t* n_acc, int32_t* n_rej);
+
+/* Time series at t_out[0..n_t), step-clipped so each t_k is hit exactly.
+ * x_out[n_traj][n_t][N]. */
+int orc_time_series(const orc_problem* pb, const orc_opts* o, const double* t_out, int32_t n_t,
+                    const int64_t* traj_ids, int64_t n_traj, int32_t n_threads, double* x_out,
+                    double* t_final, int8_t* status, int32_t* n_acc, int32_t* n_rej);
+
+/* Fixed-step classical RK4 to every t_k (steps clipped at each t_k). */
+int orc_rk4(const orc_problem* pb, const orc_opts* o, double h, const double* t_out, int32_t n_t,
+            const int64_t* traj_ids, int64_t n_traj, int32_t n_threads, double* x_out);
+
+/* Fixed-step DP5 (no control) from t0 to t_end with n_steps equal steps, for
+ * one trajectory; also returns the embedded error estimate of the last step. */
+int orc_dp5_fixed(const orc_problem* pb, const orc_opts* o, int64_t traj, int64_t n_steps,
+                  double* x_out, double* err_last);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

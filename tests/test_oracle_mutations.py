@@ -1,0 +1,109 @@
+"""Plant plausible mistakes in a copy of the oracle and check the pins catch them.
+
+Each mutation edits one spot of ``oracle/oracle.c`` (a tableau entry, the
+division of activating terms by lambda, an edge endpoint, a sign, the
+inverted sampling of inhibitory lambda, ...), compiles the copy on the CPU,
+and runs the pins of ``test_oracle_pins`` against it: at least one must fail.
+"""
+import contextlib
+import os
+import subprocess
+import tempfile
+
+import pytest
+
+import oracle
+from tests import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle")
+
+# (name, text to replace, replacement, pins expected to catch it)
+MUTATIONS = [
+    ("tableau a65", "-5103.0 / 18656", "-5103.0 / 18655",
+     [pins.test_dp5_fifth_order_on_nonlinear_motif]),
+    ("stage input drops h", "s->y[i] = x[i] + h * acc;", "s->y[i] = x[i] + acc;",
+     [pins.test_dp5_fifth_order_on_linear_decay, pins.test_dp5_fifth_order_on_nonlinear_motif]),
+    ("embedded weight b7", "1.0 / 40};", "1.0 / 41};",
+     [pins.test_embedded_error_estimate_scales_as_h5]),
+    ("activation not over lambda", "hs = hs / lam;", "hs = hs;",
+     [pins.test_hill_at_threshold_is_midpoint, pins.test_hill_limits_and_clamp]),
+    ("edge endpoint swapped", "int j = pb->src[e];", "int j = pb->dst[e];",
+     [pins.test_hill_limits_and_clamp, pins.test_cascade_fixed_point]),
+    ("degradation sign", "- (double)pb->k[i * P + p] * x[i]", "+ (double)pb->k[i * P + p] * x[i]",
+     [pins.test_edge_direction_and_degradation]),
+    ("hill numerator", "lam * b / (a + b)", "lam * a / (a + b)",
+     [pins.test_hill_limits_and_clamp]),
+    ("no clamp of negative regulator", "double B = x[j] > 0.0 ? x[j] : 0.0;", "double B = x[j];",
+     [pins.test_hill_limits_and_clamp]),
+    ("inhibitory lambda not inverted", "l = 1.0 / (inv_lo + (inv_hi - inv_lo) * u);",
+     "l = r->lam_inh_min + (r->lam_inh_max - r->lam_inh_min) * u;",
+     [pins.test_sampler_distributions]),
+    ("median of G/k", "(r->g_min + r->g_max) / (r->k_min + r->k_max)",
+     "(r->g_min + r->g_max) / 2.0 / (r->k_min + r->k_max)",
+     [pins.test_gk_median_closed_form_and_monte_carlo]),
+    ("initial state not scaled by G/k",
+     "u * (double)pb->G[i * P + p] / (double)pb->k[i * P + p]", "u * (double)pb->G[i * P + p]",
+     [pins.test_unregulated_time_series_matches_closed_form]),
+    ("philox mixing", "uint64_t n0 = hi1 ^ c1 ^ k0;", "uint64_t n0 = hi0 ^ c1 ^ k0;",
+     [pins.test_philox_matches_numpy_bit_generator]),
+    ("hill exponent", "double b = pow(B, n);", "double b = pow(B, n + 1);",
+     [pins.test_hill_half_point_for_known_power]),
+]
+
+
+@contextlib.contextmanager
+def mutated_oracle(old, new, tmpdir):
+    with open(os.path.join(SRC, "oracle.c")) as f:
+        src = f.read()
+    assert src.count(old) == 1, f"mutation anchor not unique: {old!r}"
+    path_c = os.path.join(tmpdir, "oracle.c")
+    with open(path_c, "w") as f:
+        f.write(src.replace(old, new))
+    with open(os.path.join(SRC, "oracle.h")) as f, open(os.path.join(tmpdir, "oracle.h"), "w") as g:
+        g.write(f.read())
+    so = os.path.join(tmpdir, "libmut.so")
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-pthread",
+                    path_c, "-o", so, "-lm"], check=True)
+    saved = oracle._lib
+    oracle._lib = oracle.load(so)
+    try:
+        yield
+    finally:
+        oracle._lib = saved
+
+
+def _fails(fn):
+    import inspect
+    params = inspect.signature(fn).parameters
+    try:
+        if "sign" in params and "n" in params:
+            fn(sign=-1, n=3)
+        elif "sign" in params:
+            for s in (1, -1):
+                fn(sign=s)
+        elif "n" in params:
+            fn(n=2)
+        elif "builder" in params:
+            fn(builder=pins.inputs.toggle_switch)
+        else:
+            fn()
+    except AssertionError:
+        return True
+    except (ValueError, ZeroDivisionError, FloatingPointError):
+        return True
+    return False
+
+
+@pytest.mark.parametrize("name,old,new,catchers", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pins_catch_planted_mistake(name, old, new, catchers):
+    with tempfile.TemporaryDirectory() as d, mutated_oracle(old, new, d):
+        assert any(_fails(fn) for fn in catchers), f"no pin caught mutation: {name}"
+
+
+def test_unmutated_copy_passes_the_same_pins():
+    # The harness itself must not produce failures.
+    with tempfile.TemporaryDirectory() as d, mutated_oracle("int j = pb->src[e];",
+                                                            "int j = pb->src[e];", d):
+        for _, _, _, catchers in MUTATIONS:
+            for fn in catchers:
+                assert not _fails(fn), fn.__name__
