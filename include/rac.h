@@ -1,0 +1,234 @@
+/*
+ * rac.h -- C ABI of the MI355X RACIPE ensemble integrator.
+ *
+ * RACIPE (GRiNS, arXiv 2503.18356, Sec. 2.1) turns a signed directed gene
+ * regulatory network into the ODE system of Eq. 1,
+ *
+ *   dx_i/dt = G_i * prod_{act e=(j->i)} H^S(x_j; T_e, n_e, lam_e) / lam_e
+ *                 * prod_{inh e=(j->i)} H^S(x_j; T_e, n_e, lam_e)  -  k_i * x_i,
+ *
+ * with the shifted Hill function of Eq. 2,
+ *
+ *   H^S(B; B0, n, lam) = B0^n / (B0^n + B^n) + lam * B^n / (B0^n + B^n),
+ *
+ * samples 2N + 3E parameters per parameter set (Sec. 2.1.2, Table 1) and
+ * integrates every (parameter set, initial condition) pair to a steady state
+ * or to a list of output times (Sec. 2.1.3).  This library does the sampling
+ * on the host and the integration on the GPU with hand-written HIP kernels:
+ * an adaptive Dormand-Prince 5(4) stepper with per-trajectory step control.
+ *
+ * Conventions for every entry point:
+ *   - Every call returns rac_status.  Argument errors are detected before any
+ *     work is enqueued; rac_last_error() then returns a thread-local message.
+ *   - Numerical failures of single trajectories are never return codes: they
+ *     are reported per trajectory in rac_traj_info.status.
+ *   - "dev" pointers are device memory owned by the caller (e.g. torch
+ *     tensors); "host" pointers are host memory owned by the caller.  The
+ *     library keeps no reference to caller memory after a call returns,
+ *     except that enqueued kernels read and write the dev buffers until they
+ *     complete on the given stream.
+ *   - Integration calls are stream-ordered and asynchronous: they enqueue on
+ *     hip_stream (a hipStream_t, NULL = the null stream) and return.  The
+ *     caller synchronises the stream before reading results.
+ *   - Trajectory id = p * n_ic + c for parameter set p and initial condition
+ *     c (the initial condition index runs fastest), the paper's (parameter,
+ *     initial condition) identifiers (Sec. 2.1.3).
+ *   - Edges are held in canonical order, sorted by (dst, src).  Parameter
+ *     arrays index edges in that order; rac_topology_edges() returns it.
+ */
+#ifndef RAC_H
+#define RAC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RAC_OK = 0,
+    RAC_EINVAL = -1,       /* bad argument; nothing was enqueued */
+    RAC_ENOMEM = -2,       /* host or device allocation failed */
+    RAC_EDEVICE = -3,      /* a HIP call failed */
+    RAC_EUNSUPPORTED = -4  /* valid input outside what the compiled kernels cover */
+} rac_status;
+
+/* Per-trajectory termination status. */
+typedef enum {
+    RAC_CONVERGED = 0,      /* steady-state test passed (at t0 or after a step) */
+    RAC_T_END = 1,          /* reached t_end (or the last output time) */
+    RAC_MAX_STEPS = 2,      /* more than max_steps attempted steps */
+    RAC_STEP_UNDERFLOW = 3, /* step size fell below 16 * 2^-52 * max(|t|, 1) */
+    RAC_NONFINITE = 4       /* initial state or its derivative not finite */
+} rac_traj_status;
+
+typedef enum { RAC_FP32 = 0, RAC_FP64 = 1 } rac_precision;
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* rac_last_error(void);
+
+/* Library version string. */
+const char* rac_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Topology (Sec. 2.1.1): signed directed network; sign +1 = activation,     */
+/* -1 = inhibition.  Self-loops are allowed (Sec. 3.1, 3.2).                 */
+/* ------------------------------------------------------------------------ */
+typedef struct rac_topology rac_topology;
+
+/* Copies the edge list (host arrays of length n_edges) and sorts it into
+ * canonical (dst, src) order.  EINVAL: n_genes < 1, n_edges < 0, an index out
+ * of [0, n_genes), a sign other than +-1, a duplicate (src, dst) pair, or a
+ * NULL array with n_edges > 0.  EUNSUPPORTED: n_genes > 4096 or n_edges >
+ * 32767.  The handle is immutable and safe to share across threads; device
+ * copies of its lane plans are made lazily and cached in it.  Free it with
+ * rac_destroy_topology. */
+rac_status rac_create_topology(int32_t n_genes, int32_t n_edges, const int32_t* src,
+                               const int32_t* dst, const int8_t* sign, rac_topology** out);
+
+/* Frees the handle and its device copies.  The caller must ensure no enqueued
+ * work still uses it.  NULL is a no-op. */
+void rac_destroy_topology(rac_topology* topo);
+
+/* Sizes of a topology. */
+rac_status rac_topology_size(const rac_topology* topo, int32_t* n_genes, int32_t* n_edges);
+
+/* Canonical edge order: host arrays of length n_edges (any may be NULL). */
+rac_status rac_topology_edges(const rac_topology* topo, int32_t* src, int32_t* dst, int8_t* sign);
+
+/* ------------------------------------------------------------------------ */
+/* Sampling (Sec. 2.1.2, Table 1).                                           */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double g_min, g_max;          /* production rate G: Table 1 [1, 100] */
+    double k_min, k_max;          /* degradation rate k: [0.1, 1] */
+    double lam_act_min, lam_act_max; /* activating fold change: [1, 100] */
+    double lam_inh_min, lam_inh_max; /* inhibiting fold change: [0.01, 1],
+                                        sampled uniformly in the inverse range
+                                        [1/max, 1/min] and inverted */
+    int32_t n_min, n_max;         /* integer Hill coefficient: [1, 6] */
+    double t_lo, t_hi;            /* threshold window: [0.02, 1.98] x median */
+    double t_median;              /* <= 0: the median of G/k implied by the
+                                     G and k ranges (1010/11 for Table 1) */
+} rac_ranges;
+
+/* Table 1 defaults. */
+void rac_default_ranges(rac_ranges* r);
+
+/* Caller-owned parameter arrays, set index fastest (SoA), stride n_sets:
+ *   G[i * n_sets + p], k[i * n_sets + p]            for genes i < N,
+ *   T[e * n_sets + p], lam[e * n_sets + p], n[...]  for canonical edges e < E.
+ * lam is the fold change of Table 1 (activation >= 1, inhibition <= 1).  The
+ * same struct describes host arrays (rac_sample_params) and device arrays
+ * (integration calls). */
+typedef struct {
+    float* G;
+    float* k;
+    float* T;
+    float* lam;
+    uint8_t* n;
+    int64_t n_sets;
+} rac_params_view;
+
+/* Deterministic, index-addressable sampling on the host: set p depends only
+ * on (seed, p), so sets [set_begin, set_begin + n_sets) come out the same
+ * whatever the batch.  Each parameter is drawn from Philox4x64-10 (Salmon et
+ * al. 2011; counter (p, slot / 4, 0, 0), key (seed, 0), word slot % 4, top 53
+ * bits scaled to [0, 1); slots G_i = i, k_i = N + i, T_e = 2N + 3e,
+ * n_e = 2N + 3e + 1, lam_e = 2N + 3e + 2), mapped to its range in FP64 and
+ * rounded to FP32.  Thresholds are uniform in [t_lo, t_hi] times the median
+ * of G/k (the half-functional window of Sec. 2.1.2 with the prior median).
+ * Initial-condition fractions ic_frac[c * N + i] (host, may be NULL) in
+ * [0, 1) use counter (c, i / 4, 1, 0): they are shared by all parameter sets
+ * (Sec. 3.1).  out->n_sets must equal n_sets.  ranges NULL = Table 1.
+ * EINVAL: NULL arrays, n_sets < 0, n_ic < 0, or inverted/non-positive ranges. */
+rac_status rac_sample_params(const rac_topology* topo, const rac_ranges* ranges, uint64_t seed,
+                             int64_t set_begin, int64_t n_sets, int32_t n_ic,
+                             rac_params_view* out, float* ic_frac);
+
+/* ------------------------------------------------------------------------ */
+/* Integration (Sec. 2.1.3).                                                  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double t0;          /* start time (default 0) */
+    double t_end;       /* hard stop even if not steady (default 200) */
+    double rtol, atol;  /* error control (defaults 1e-6, 1e-9) */
+    double ss_atol;     /* steady when every |dx_i/dt| <= ss_atol + ss_rtol * k_i * |x_i| */
+    double ss_rtol;     /* default 0 for FP64, 1e-5 for FP32 (FP32 rounding floor of f) */
+    double h0;          /* first step; <= 0 picks it automatically */
+    int64_t max_steps;  /* attempted steps per trajectory (default 100000) */
+    int32_t precision;  /* RAC_FP32: FP32 state and right-hand side, FP64 time,
+                           error norm and steady test.  RAC_FP64: all FP64. */
+    int32_t activation_divides_by_lambda; /* 1 (default) = Eq. 1 as printed */
+    int32_t stop_at_steady; /* time series only: stop once steady and fill the
+                               remaining output times with x_ss (default 0) */
+    int32_t ic_absolute;    /* 1: ic holds absolute levels instead of fractions
+                               of G_i/k_i, e.g. to pin input nodes (Sec. 3.2) */
+    int32_t lanes_per_traj; /* 0 = automatic; else 1, 2, 4, ..., 64 */
+    int32_t refill_min;     /* 0 = automatic: a wave pulls new trajectories from
+                               the work queue once this many of its trajectory
+                               groups are free (each refill costs the wave two
+                               right-hand sides); always 1 near the queue end */
+} rac_solver_opts;
+
+/* Defaults for a precision. */
+void rac_default_opts(rac_solver_opts* o, int32_t precision);
+
+/* Per-trajectory outputs, device arrays of length P * n_ic (any may be NULL). */
+typedef struct {
+    double* t_final;     /* time at termination */
+    int8_t* status;      /* rac_traj_status */
+    int32_t* n_accepted; /* accepted steps */
+    int32_t* n_rejected; /* rejected steps */
+} rac_traj_info;
+
+/* Integrates all P * n_ic trajectories (P = dev_params->n_sets) from
+ * x0_i = ic[c][i] * G_i / k_i (or ic[c][i] with ic_absolute) to a steady state
+ * or t_end.  dev_ic: device [n_ic][N] f32.  dev_x_out: device
+ * [P * n_ic][N], f32 for RAC_FP32 and f64 for RAC_FP64.  A single combination
+ * (Sec. 2.1.3) is P = n_ic = 1.  P * n_ic = 0 enqueues nothing.
+ * EINVAL: NULL handle/opts/arrays, n_ic < 1, t_end <= t0, rtol < 0, atol < 0,
+ * rtol + atol == 0, ss_atol < 0, max_steps < 1, bad precision.
+ * EUNSUPPORTED: the network does not fit the compiled lane plans. */
+rac_status rac_steady_states(const rac_topology* topo, const rac_params_view* dev_params,
+                             const float* dev_ic, int32_t n_ic, const rac_solver_opts* opts,
+                             void* dev_x_out, const rac_traj_info* dev_info, void* hip_stream);
+
+/* Time series at host_t_out[0..n_t) (strictly increasing, >= t0; Sec. 2.1.3):
+ * integrates to the last output time; each output is the DP5 continuous
+ * extension (Hairer, Norsett, Wanner I, Sec. II.6) at that time.
+ * dev_x_out: device [P * n_ic][n_t][N] (f32 or f64 by precision).  opts->t_end
+ * is ignored.  Status T_END means the last output time was reached.
+ * EINVAL as rac_steady_states, plus n_t < 1 or unordered / early times. */
+rac_status rac_integrate(const rac_topology* topo, const rac_params_view* dev_params,
+                         const float* dev_ic, int32_t n_ic, const rac_solver_opts* opts,
+                         const double* host_t_out, int32_t n_t, void* dev_x_out,
+                         const rac_traj_info* dev_info, void* hip_stream);
+
+/* One work item of a fused multi-network launch. */
+typedef struct {
+    const rac_topology* topo;
+    rac_params_view params;  /* device arrays */
+    const float* ic;         /* device [n_ic][N] */
+    int32_t n_ic;
+    void* x_out;             /* device [P * n_ic][N] */
+    rac_traj_info info;      /* device arrays */
+} rac_batch_item;
+
+/* Steady states of several networks of uneven size in persistent launches
+ * that pull trajectories from one device work queue (networks sharing a
+ * kernel shape go into the same launch; lanes freed by converged trajectories
+ * are refilled from the queue).  Results per item are as rac_steady_states
+ * with the same opts.  EINVAL as rac_steady_states for any item. */
+rac_status rac_steady_states_batch(const rac_batch_item* items, int32_t n_items,
+                                   const rac_solver_opts* opts, void* hip_stream);
+
+/* The lanes-per-trajectory choice the library would make for a network
+ * (0 if none fits), and whether a given choice fits the compiled kernels. */
+int32_t rac_auto_lanes(const rac_topology* topo, int32_t precision);
+int32_t rac_lanes_supported(const rac_topology* topo, int32_t precision, int32_t lanes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

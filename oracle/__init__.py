@@ -229,7 +229,7 @@ class Result:
 
 
 def default_threads() -> int:
-    return max(1, min(os.cpu_count() or 1, 64))
+    return max(1, min(os.cpu_count() or 1, 16))
 
 
 def rhs(net: Network, prm: Params, p: int, x, divide: int = 1) -> np.ndarray:

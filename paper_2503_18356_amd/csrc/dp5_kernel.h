@@ -1,0 +1,492 @@
+// The persistent DP5(4) ensemble kernel, templated on the state precision R,
+// the compiled edge-slot and gene-slot budgets (EPL, GPL) and the output mode
+// (steady state or time series).  Included by the per-precision translation
+// units that instantiate it.
+#pragma once
+
+#include "kernel_common.h"
+
+namespace rac {
+
+// Dormand & Prince (1980) 5(4) tableau (Hairer, Norsett, Wanner I, Table 5.2).
+// Row s holds the weights of k_1..k_s in the input of stage s+1; row 6 is the
+// fifth-order solution (first same as last).
+__device__ constexpr double kA[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5, 0, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+    {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84},
+};
+// Fifth- minus fourth-order weights (the embedded error estimate).
+__device__ constexpr double kErr[7] = {
+    35.0 / 384 - 5179.0 / 57600,     0.0,
+    500.0 / 1113 - 7571.0 / 16695,   125.0 / 192 - 393.0 / 640,
+    -2187.0 / 6784 + 92097.0 / 339200, 11.0 / 84 - 187.0 / 2100,
+    -1.0 / 40};
+// Dense output (continuous extension of order 4, Hairer, Norsett, Wanner I,
+// Sec. II.6): weights of k_1, k_3..k_7 in the fifth interpolation coefficient.
+__device__ constexpr double kDense[7] = {
+    -12715105075.0 / 11282082432.0, 0.0,
+    87487479700.0 / 32700410799.0,  -10690763975.0 / 1880347072.0,
+    701980252875.0 / 199316789632.0, -1453857185.0 / 822651844.0,
+    69997945.0 / 29380423.0};
+
+// Transcendentals: hardware v_log/v_exp/v_rcp for FP32; exact routines and
+// an integer power for FP64.
+template <typename R>
+struct Ops;
+
+template <>
+struct Ops<float> {
+    using NType = float;
+    __device__ static float to_n(int n) { return (float)n; }
+    // Shifted Hill factor divided by sqrt(lambda):
+    //   H^S / sqrt(lam) = beta' + delta' / (1 + (x/T)^n),
+    //   beta' = sqrt(lam), delta' = 1/sqrt(lam) - sqrt(lam).
+    __device__ static float hill(float xs, float invT, float n, float b, float d) {
+        const float q = xs * invT;
+        const float r = __builtin_amdgcn_exp2f(n * __builtin_amdgcn_logf(q));
+        return __builtin_fmaf(d, __builtin_amdgcn_rcpf(1.0f + r), b);
+    }
+    __device__ static float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
+    __device__ static float sqrt(float v) { return __builtin_sqrtf(v); }
+    // Step factor err^(-1/5) (FP32 is ample for a controller factor).
+    __device__ static double pow_m15(double err) {
+        return (double)__builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf((float)err));
+    }
+};
+
+template <>
+struct Ops<double> {
+    using NType = int;
+    __device__ static int to_n(int n) { return n; }
+    __device__ static double hill(double xs, double invT, int n, double b, double d) {
+        const double q = xs * invT;
+        double r = 1.0, base = q;
+        for (int e = n; e > 0; e >>= 1) {
+            if (e & 1) r *= base;
+            base *= base;
+        }
+        return fma(d, 1.0 / (1.0 + r), b);
+    }
+    __device__ static double rcp(double v) { return 1.0 / v; }
+    __device__ static double sqrt(double v) { return ::sqrt(v); }
+    __device__ static double pow_m15(double err) { return ::pow(err, -0.2); }
+};
+
+// Wave-level ordering of LDS writes before reads by other lanes of the wave.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+enum : int { kRunning = -1 };
+
+template <typename R, int EPL, int GPL, bool TS>
+__global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
+    using O = Ops<R>;
+    using NT = typename O::NType;
+    constexpr int kSlots = GPL + EPL + 1;
+    __shared__ R lds[kBlock / 64][64 * kSlots];
+
+    const int lane = threadIdx.x & 63;
+    R* const lx = lds[threadIdx.x >> 6];  // [gene][group] source levels
+    R* const lp = lx + 64 * GPL;          // [slot][lane] running products
+
+    const int lpt = a.lpt;
+    const int sh = __builtin_ctz(lpt);
+    const int n_groups = 64 >> sh;
+    const int g = lane >> sh;   // group within the wave
+    const int r = lane & (lpt - 1);  // lane within the group
+    const uint64_t gmask = lpt == 64 ? ~0ull : (((1ull << lpt) - 1) << (g * lpt));
+    const int epl_rt = a.epl, gpl_rt = a.gpl;
+    const Controls& c = a.c;
+
+    lp[lane] = (R)1;  // prefix[0] = 1
+
+    // Per-lane edge slots.
+    int e_src[EPL];
+    R e_invT[EPL], e_b[EPL], e_d[EPL];
+    NT e_n[EPL];
+    // Per-lane gene slots.
+    R x[GPL], y[GPL], kk[7][GPL], gG[GPL], gk[GPL];
+    int g_pb[GPL], g_pe[GPL], g_xi[GPL], g_id[GPL];
+#pragma unroll
+    for (int s = 0; s < EPL; ++s) {
+        e_src[s] = g; e_invT[s] = 0; e_b[s] = 1; e_d[s] = 0; e_n[s] = O::to_n(1);
+    }
+#pragma unroll
+    for (int q = 0; q < GPL; ++q) {
+        x[q] = 0; y[q] = 0; gG[q] = 0; gk[q] = 0;
+        g_pb[q] = lane; g_pe[q] = lane; g_xi[q] = 0; g_id[q] = -1;
+#pragma unroll
+        for (int l = 0; l < 7; ++l) kk[l][q] = 0;
+    }
+
+    // Per-group scalars (replicated over the group's lanes).
+    int64_t traj = -1, local = 0;
+    int net = 0, kout = 0, nacc = 0, nrej = 0;
+    bool fresh = false, last_rej = false;
+    double t = 0, h = 0, t_stop = 0;
+    bool exhausted = false;
+    uint64_t popped = 0;  // queue position after this wave's last pop
+    int n_genes = 1;
+
+    // Network descriptor by value: from the device table or the kernel argument.
+    auto desc = [&](int id) -> NetDesc { return a.nets ? a.nets[id] : a.net0; };
+
+    // One right-hand-side evaluation f(yv) for every lane of the wave.
+    auto rhs = [&](const R (&yv)[GPL], R (&f)[GPL]) {
+#pragma unroll
+        for (int q = 0; q < GPL; ++q)
+            if (q < gpl_rt && g_id[q] >= 0) lx[g_xi[q]] = yv[q] > (R)0 ? yv[q] : (R)0;
+        wave_sync();
+        R run = 1;
+#pragma unroll
+        for (int s = 0; s < EPL; ++s) {
+            if (s < epl_rt) {
+                run *= O::hill(lx[e_src[s]], e_invT[s], e_n[s], e_b[s], e_d[s]);
+                lp[(s + 1) * 64 + lane] = run;
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (int q = 0; q < GPL; ++q)
+            f[q] = q < gpl_rt ? gG[q] * (lp[g_pe[q]] * O::rcp(lp[g_pb[q]])) - gk[q] * yv[q] : (R)0;
+    };
+
+    auto group_sum = [&](double v) {
+        for (int m = 1; m < lpt; m <<= 1) v += __shfl_xor(v, m);
+        return v;
+    };
+    auto group_all = [&](bool p) { return (__ballot(p) & gmask) == gmask; };
+
+    // Write the end-of-trajectory record and free the group.
+    auto finish = [&](int status) {
+        const NetDesc d = desc(net);
+        if (!TS) {
+            R* xo = (R*)d.x_out + local * d.n_genes;
+#pragma unroll
+            for (int q = 0; q < GPL; ++q)
+                if (q < gpl_rt && g_id[q] >= 0) xo[g_id[q]] = x[q];
+        } else {
+            // Steady before the last output: the remaining outputs hold x_ss.
+            R* xo = (R*)d.x_out + local * (int64_t)a.n_t * d.n_genes;
+            for (int k = kout; k < a.n_t; ++k)
+#pragma unroll
+                for (int q = 0; q < GPL; ++q)
+                    if (q < gpl_rt && g_id[q] >= 0) xo[(int64_t)k * d.n_genes + g_id[q]] = x[q];
+        }
+        if (r == 0) {
+            if (d.t_final) d.t_final[local] = t;
+            if (d.status) d.status[local] = (int8_t)status;
+            if (d.n_acc) d.n_acc[local] = nacc;
+            if (d.n_rej) d.n_rej[local] = nrej;
+        }
+        traj = -1;
+        fresh = false;
+    };
+
+    for (;;) {
+        // ---- refill free groups from the work queue --------------------
+        if (!exhausted) {
+            const uint64_t free_lead = __ballot(traj < 0 && r == 0);
+            const int nfree = __popcll(free_lead);
+            const uint64_t busy_lead = __ballot(traj >= 0 && r == 0);
+            // Refill in batches (each refill costs the wave two extra right-hand
+            // sides), but take single items once the queue is nearly drained.
+            const bool near_end = (uint64_t)a.total - popped < (uint64_t)gridDim.x * (kBlock / 64) * 64;
+            if (nfree > 0 && (nfree >= c.refill_min || busy_lead == 0 || near_end)) {
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(a.counter, (unsigned long long)nfree);
+                base = __shfl(base, 0);
+                popped = base + (unsigned long long)nfree;
+                if (base + (unsigned long long)nfree >= (unsigned long long)a.total) exhausted = true;
+                if (traj < 0) {
+                    const int rank = __popcll(free_lead & ((1ull << (g * lpt)) - 1ull));
+                    const int64_t idx = (int64_t)base + rank;
+                    if (idx < a.total) {
+                        // Which network: binary search over first queue indices.
+                        net = 0;
+                        if (a.nets) {
+                            int lo = 0, hi = a.n_nets - 1;
+                            while (lo < hi) {
+                                const int mid = (lo + hi + 1) >> 1;
+                                if (a.nets[mid].traj_begin <= idx) lo = mid; else hi = mid - 1;
+                            }
+                            net = lo;
+                        }
+                        // Loads go one slot at a time (the memory clobbers stop
+                        // the scheduler from hoisting them all), which keeps
+                        // this rarely taken path from setting the kernel's
+                        // register peak next to the live trajectory state.
+#define RAC_DF(field) (a.nets ? a.nets[net].field : a.net0.field)
+                        traj = idx;
+                        local = idx - RAC_DF(traj_begin);
+                        const int n_ic = RAC_DF(n_ic);
+                        int64_t p = (int64_t)((double)local * RAC_DF(inv_n_ic));
+                        if (p * n_ic > local) --p;
+                        if ((p + 1) * n_ic <= local) ++p;
+                        const int ci = (int)(local - p * n_ic);
+                        const int64_t P = RAC_DF(n_sets);
+                        n_genes = RAC_DF(n_genes);
+                        const int stride = RAC_DF(stride);
+                        const int32_t* lane_edge = RAC_DF(lane_edge) + r * stride;
+                        const float* Tp = RAC_DF(T) + p;
+                        const float* Lp = RAC_DF(lam) + p;
+                        const uint8_t* Np = RAC_DF(n) + p;
+#pragma unroll
+                        for (int s = 0; s < EPL; ++s) {
+                            asm volatile("" ::: "memory");
+                            const int pk = (s < epl_rt && s < stride) ? lane_edge[s] : -1;
+                            if (pk >= 0) {
+                                const int e = pk & 0xffff, src = pk >> 16;
+                                const R Tv = (R)Tp[e * P];
+                                const R sl = O::sqrt((R)Lp[e * P]);
+                                e_src[s] = src * n_groups + g;
+                                e_invT[s] = (R)1 / Tv;
+                                e_n[s] = O::to_n((int)Np[e * P]);
+                                e_b[s] = sl;
+                                e_d[s] = (R)1 / sl - sl;
+                            } else {
+                                e_src[s] = g; e_invT[s] = 0; e_b[s] = 1; e_d[s] = 0; e_n[s] = O::to_n(1);
+                            }
+                        }
+                        const float* Gp = RAC_DF(G) + p;
+                        const float* Kp = RAC_DF(k) + p;
+                        const float* icp = RAC_DF(ic) + (int64_t)ci * n_genes;
+                        const int32_t* row_ptr = RAC_DF(row_ptr);
+                        const int32_t* gene_row = RAC_DF(gene_row);
+                        const int8_t* sign = RAC_DF(sign);
+#pragma unroll
+                        for (int q = 0; q < GPL; ++q) {
+                            asm volatile("" ::: "memory");
+                            const int gene = r + q * lpt;
+                            if (q < gpl_rt && gene < n_genes) {
+                                const R Gv = (R)Gp[gene * P];
+                                const R kv = (R)Kp[gene * P];
+                                // Fold each row's sqrt(lam) (and, for activation
+                                // over lambda, 1/lam) into the production rate.
+                                R gf = Gv;
+                                for (int e = row_ptr[gene]; e < row_ptr[gene + 1]; ++e) {
+                                    const R sl = O::sqrt((R)Lp[e * P]);
+                                    gf *= (sign[e] > 0 && c.divide) ? (R)1 / sl : sl;
+                                }
+                                const int row = gene_row[gene];
+                                const int rl = row & 0xff, pb = (row >> 8) & 0xff, pe = (row >> 16) & 0xff;
+                                const int rowlane = g * lpt + rl;
+                                g_id[q] = gene;
+                                g_xi[q] = gene * n_groups + g;
+                                g_pb[q] = pb * 64 + rowlane;
+                                g_pe[q] = pe * 64 + rowlane;
+                                gG[q] = gf;
+                                gk[q] = kv;
+                                const R u = (R)icp[gene];
+                                x[q] = c.ic_absolute ? u : u * Gv / kv;
+                            } else {
+                                g_id[q] = -1; g_xi[q] = 0; g_pb[q] = lane; g_pe[q] = lane;
+                                gG[q] = 0; gk[q] = 0; x[q] = 0;
+                            }
+                        }
+#undef RAC_DF
+                        t = c.t0;
+                        t_stop = TS ? a.t_out[a.n_t - 1] : c.t_end;
+                        nacc = 0; nrej = 0; kout = 0; last_rej = false;
+                        fresh = true;
+                    }
+                }
+            }
+        }
+        if (__ballot(traj >= 0) == 0) {
+            if (exhausted) break;
+            continue;
+        }
+
+        // ---- start new trajectories: f(x0), steady test at t0, first step -
+        if (__ballot(fresh) != 0) {
+#pragma unroll
+            for (int q = 0; q < GPL; ++q) y[q] = x[q];
+            rhs(y, kk[1]);
+            bool fin = true;
+            double s0 = 0, s1 = 0;
+#pragma unroll
+            for (int q = 0; q < GPL; ++q) {
+                if (fresh) kk[0][q] = kk[1][q];
+                if (q < gpl_rt && g_id[q] >= 0) {
+                    fin = fin && __builtin_isfinite((double)x[q]) && __builtin_isfinite((double)kk[1][q]);
+                    const double isc = 1.0 / (c.atol + c.rtol * fabs((double)x[q]));
+                    s0 += ((double)x[q] * isc) * ((double)x[q] * isc);
+                    s1 += ((double)kk[1][q] * isc) * ((double)kk[1][q] * isc);
+                }
+            }
+            const bool all_fin = group_all(fin);
+            bool steady = true;
+#pragma unroll
+            for (int q = 0; q < GPL; ++q)
+                if (q < gpl_rt && g_id[q] >= 0)
+                    steady = steady && fabs((double)kk[1][q]) <=
+                                           c.ss_atol + c.ss_rtol * (double)gk[q] * fabs((double)x[q]);
+            const bool all_steady = group_all(steady);
+            const double d0 = sqrt(group_sum(s0) / n_genes), d1 = sqrt(group_sum(s1) / n_genes);
+            if (TS && fresh) {
+                const NetDesc d = desc(net);
+                R* xo = (R*)d.x_out + local * (int64_t)a.n_t * d.n_genes;
+                while (kout < a.n_t && a.t_out[kout] <= t) {
+#pragma unroll
+                    for (int q = 0; q < GPL; ++q)
+                        if (q < gpl_rt && g_id[q] >= 0) xo[(int64_t)kout * d.n_genes + g_id[q]] = x[q];
+                    ++kout;
+                }
+            }
+            const double hmax = t_stop - c.t0;
+            double hg = (d0 < 1e-10 || d1 < 1e-10) ? 1e-6 : 0.01 * d0 / d1;
+            hg = hg < hmax ? hg : hmax;
+#pragma unroll
+            for (int q = 0; q < GPL; ++q) y[q] = x[q] + (R)hg * kk[0][q];
+            rhs(y, kk[2]);
+            double s2 = 0;
+#pragma unroll
+            for (int q = 0; q < GPL; ++q)
+                if (q < gpl_rt && g_id[q] >= 0) {
+                    const double dv = ((double)kk[2][q] - (double)kk[0][q]) /
+                                      (c.atol + c.rtol * fabs((double)x[q]));
+                    s2 += dv * dv;
+                }
+            const double d2 = sqrt(group_sum(s2) / n_genes) / hg;
+            if (fresh) {
+                if (!all_fin) {
+                    finish(RAC_NONFINITE);
+                } else if ((!TS || c.stop_at_steady) && all_steady) {
+                    finish(RAC_CONVERGED);
+                } else if (t >= t_stop) {
+                    finish(RAC_T_END);
+                } else if (c.h0 > 0) {
+                    h = c.h0 < hmax ? c.h0 : hmax;
+                    fresh = false;
+                } else {
+                    const double der = d1 > d2 ? d1 : d2;
+                    const double h1 = der <= 1e-15 ? (1e-6 > hg * 1e-3 ? 1e-6 : hg * 1e-3)
+                                                   : ::pow(0.01 / der, 0.2);
+                    double hh = 100.0 * hg < h1 ? 100.0 * hg : h1;
+                    h = hh <= hmax ? hh : hmax;
+                    fresh = false;
+                }
+            }
+            continue;
+        }
+
+        // ---- one DP5 attempt for every running group ---------------------
+        const bool running = traj >= 0;
+        int stop_status = kRunning;
+        if (running) {
+            const double tmag = fabs(t) > 1.0 ? fabs(t) : 1.0;
+            if ((int64_t)nacc + nrej >= c.max_steps) stop_status = RAC_MAX_STEPS;
+            else if (h < 16.0 * 2.220446049250313e-16 * tmag) stop_status = RAC_STEP_UNDERFLOW;
+        }
+        if (__ballot(running && stop_status != kRunning) != 0) {
+            if (running && stop_status != kRunning) finish(stop_status);
+            continue;
+        }
+        double hs = h;
+        bool clipped = false;
+        if (t + hs >= t_stop) {
+            hs = t_stop - t;
+            clipped = true;
+        }
+        const R hR = (R)hs;
+#pragma unroll
+        for (int st = 1; st < 7; ++st) {
+#pragma unroll
+            for (int q = 0; q < GPL; ++q) {
+                R acc = (R)kA[st][0] * kk[0][q];
+#pragma unroll
+                for (int l = 1; l < st; ++l)
+                    if (kA[st][l] != 0.0) acc += (R)kA[st][l] * kk[l][q];
+                y[q] = x[q] + hR * acc;
+            }
+            rhs(y, kk[st]);
+        }
+        // y now holds the fifth-order solution, kk[6] its derivative.
+        double serr = 0;
+        bool fin = true;
+#pragma unroll
+        for (int q = 0; q < GPL; ++q) {
+            if (q < gpl_rt && g_id[q] >= 0) {
+                R e = (R)kErr[0] * kk[0][q];
+#pragma unroll
+                for (int l = 2; l < 7; ++l) e += (R)kErr[l] * kk[l][q];
+                // Scaled error e_i / (atol + rtol max(|x_i|, |x_new,i|)); the
+                // ratio in R, its square accumulated in FP64.
+                const R ax = x[q] < 0 ? -x[q] : x[q], an = y[q] < 0 ? -y[q] : y[q];
+                const R sc = (R)c.atol + (R)c.rtol * (ax > an ? ax : an);
+                const double rq = (double)(hR * e * O::rcp(sc));
+                serr += rq * rq;
+                fin = fin && __builtin_isfinite((double)y[q]);
+            }
+        }
+        const double err = sqrt(group_sum(serr) / n_genes);
+        const bool all_fin = group_all(fin);  // collective: evaluated by every lane
+        const bool accept = running && all_fin && __builtin_isfinite(err) && err <= 1.0;
+        if (running && !accept) {
+            ++nrej;
+            double fac = __builtin_isfinite(err) ? 0.9 * O::pow_m15(err) : 0.2;
+            fac = fac < 0.2 ? 0.2 : (fac > 1.0 ? 1.0 : fac);
+            h = hs * fac;
+            last_rej = true;
+        }
+        // Dense output for every output time inside the accepted step.
+        if (TS && accept && kout < a.n_t && a.t_out[kout] <= (clipped ? t_stop : t + hs)) {
+            const NetDesc d = desc(net);
+            R* xo = (R*)d.x_out + local * (int64_t)a.n_t * d.n_genes;
+            const double t_new = clipped ? t_stop : t + hs;
+            while (kout < a.n_t && a.t_out[kout] <= t_new) {
+                const R th = (R)((a.t_out[kout] - t) / hs);
+                const R th1 = (R)1 - th;
+#pragma unroll
+                for (int q = 0; q < GPL; ++q) {
+                    if (q < gpl_rt && g_id[q] >= 0) {
+                        const R ydiff = y[q] - x[q];
+                        const R bspl = hR * kk[0][q] - ydiff;
+                        const R c4 = ydiff - hR * kk[6][q] - bspl;
+                        R c5 = (R)kDense[0] * kk[0][q];
+#pragma unroll
+                        for (int l = 2; l < 7; ++l) c5 += (R)kDense[l] * kk[l][q];
+                        c5 *= hR;
+                        const R v = x[q] + th * (ydiff + th1 * (bspl + th * (c4 + th1 * c5)));
+                        xo[(int64_t)kout * d.n_genes + g_id[q]] = v;
+                    }
+                }
+                ++kout;
+            }
+        }
+        bool steady = true;
+        if (accept) {
+            ++nacc;
+            t = clipped ? t_stop : t + hs;
+#pragma unroll
+            for (int q = 0; q < GPL; ++q) {
+                x[q] = y[q];
+                kk[0][q] = kk[6][q];
+                if (q < gpl_rt && g_id[q] >= 0)
+                    steady = steady && fabs((double)kk[0][q]) <=
+                                           c.ss_atol + c.ss_rtol * (double)gk[q] * fabs((double)x[q]);
+            }
+            double fac = err > 0 ? 0.9 * O::pow_m15(err) : 10.0;
+            const double fmax = last_rej ? 1.0 : 10.0;
+            fac = fac > fmax ? fmax : (fac < 0.2 ? 0.2 : fac);
+            h = hs * fac;
+            last_rej = false;
+        }
+        const bool all_steady = group_all(steady);
+        if (accept) {
+            if ((!TS || c.stop_at_steady) && all_steady) finish(RAC_CONVERGED);
+            else if (t >= t_stop) finish(RAC_T_END);
+        }
+    }
+}
+
+}  // namespace rac

@@ -1,0 +1,67 @@
+// Device-side structures and the persistent Dormand-Prince 5(4) kernel body.
+//
+// Mapping (CDNA4, wave64): a wave holds 64 / L trajectory groups of L lanes.
+// Each lane owns ceil(N / L) genes (their DP5 state lives in its VGPRs) and a
+// balanced set of whole in-edge rows (their per-trajectory edge parameters
+// live in its VGPRs).  One right-hand-side evaluation is
+//   1. owners publish max(y_i, 0) to LDS,
+//   2. every lane walks its edge slots: read the source level from LDS,
+//      evaluate the shifted Hill factor, keep a running product in LDS,
+//   3. owners read prefix[end] / prefix[begin] of their row and form
+//      f_i = G_i' * P_i - k_i * y_i.
+// Step control, the error norm and the steady test are per group; groups
+// that finish are refilled from a device work queue (one atomic per wave).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "rac.h"
+
+namespace rac {
+
+struct NetDesc {
+    const int32_t* lane_edge;  // [lpt][stride] packed (edge | src << 16), -1 empty
+    const int32_t* gene_row;   // [N] packed row lane | begin << 8 | end << 16
+    const int32_t* row_ptr;    // [N + 1]
+    const int8_t* sign;        // [E]
+    const float* G;
+    const float* k;
+    const float* T;
+    const float* lam;
+    const uint8_t* n;
+    const float* ic;           // [n_ic][N]
+    void* x_out;
+    double* t_final;
+    int8_t* status;
+    int32_t* n_acc;
+    int32_t* n_rej;
+    int64_t n_sets;            // parameter array stride P
+    int64_t traj_begin;        // first queue index of this network
+    int64_t n_traj;            // P * n_ic
+    double inv_n_ic;           // 1 / n_ic
+    int32_t n_genes, n_edges, n_ic, stride;
+};
+
+struct Controls {
+    double t0, t_end, rtol, atol, ss_atol, ss_rtol, h0;
+    int64_t max_steps;
+    int32_t divide, ic_absolute, stop_at_steady, refill_min;
+};
+
+struct LaunchArgs {
+    const NetDesc* nets;  // device array when n_nets > 1, else nullptr
+    NetDesc net0;         // the network when nets == nullptr
+    int32_t n_nets;
+    int64_t total;        // trajectories over all networks
+    unsigned long long* counter;
+    int32_t lpt, epl, gpl;  // lanes per trajectory; runtime slot bounds
+    const double* t_out;    // device, time-series mode
+    int32_t n_t;
+    Controls c;
+};
+
+constexpr int kBlock = 256;  // 4 independent waves per block
+
+}  // namespace rac

@@ -1,0 +1,25 @@
+// Registry of the compiled kernel instantiations.
+#pragma once
+
+#include "kernel_common.h"
+
+namespace rac {
+
+using KernelFn = void (*)(LaunchArgs);
+
+struct KernelEntry {
+    int precision;  // RAC_FP32 / RAC_FP64
+    bool ts;        // time-series mode
+    int epl, gpl;   // compiled slot budgets
+    const void* fn; // __global__ function
+};
+
+// Each instantiation unit appends its entries.
+int kernels_f32_ss(const KernelEntry** out);
+int kernels_f32_ts(const KernelEntry** out);
+int kernels_f64_ss(const KernelEntry** out);
+int kernels_f64_ts(const KernelEntry** out);
+
+const KernelEntry* find_kernel(int precision, bool ts, int epl, int gpl);
+
+}  // namespace rac

@@ -1,0 +1,21 @@
+// Instantiations of the DP5(4) kernel: float state, steady-state mode.
+#include "dp5_kernel.h"
+#include "kernel_table.h"
+#include "rac.h"
+
+namespace rac {
+
+#define RAC_K(E, G) {RAC_FP32, false, E, G, reinterpret_cast<const void*>(&dp5_kernel<float, E, G, false>)}
+
+static const KernelEntry kTable[] = {
+    RAC_K(4, 1),  RAC_K(4, 2),  RAC_K(4, 4),  RAC_K(4, 8),  RAC_K(8, 1),
+    RAC_K(8, 2),  RAC_K(8, 4),  RAC_K(8, 8),  RAC_K(16, 1), RAC_K(16, 2),
+    RAC_K(16, 4), RAC_K(16, 8), RAC_K(32, 1), RAC_K(32, 2), RAC_K(32, 4),
+};
+
+int kernels_f32_ss(const KernelEntry** out) {
+    *out = kTable;
+    return (int)(sizeof(kTable) / sizeof(kTable[0]));
+}
+
+}  // namespace rac

@@ -1,0 +1,85 @@
+// Internal declarations shared by the host code and the HIP kernels.
+#pragma once
+
+#include <cstdint>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "rac.h"
+
+namespace rac {
+
+// Largest network the lane plans address: src gene and edge id are packed in
+// 16 bits each.
+constexpr int kMaxGenes = 4096;
+constexpr int kMaxEdges = 32767;
+constexpr int kWave = 64;
+
+// Compiled kernel shapes: edge slots per lane (EPL) and gene slots per lane
+// (GPL) are compile-time register budgets; the counts actually used are
+// runtime bounds <= these.
+struct Shape {
+    int epl, gpl;
+};
+constexpr Shape kShapesF32[] = {{4, 1},  {4, 2},  {4, 4},  {4, 8},  {8, 1},
+                                {8, 2},  {8, 4},  {8, 8},  {16, 1}, {16, 2},
+                                {16, 4}, {16, 8}, {32, 1}, {32, 2}, {32, 4}};
+constexpr Shape kShapesF64[] = {{4, 1}, {4, 2}, {4, 4},  {8, 1}, {8, 2},
+                                {8, 4}, {16, 1}, {16, 2}, {32, 1}};
+
+// How one network is spread over the lanes of a trajectory group.
+struct LanePlan {
+    int lpt = 0;      // lanes per trajectory (power of two, <= 64)
+    int epl = 0;      // edge slots used per lane (max over lanes)
+    int stride = 1;   // row stride of lane_edge = max(epl, 1)
+    int gpl = 0;      // gene slots used per lane = ceil(N / lpt)
+    // [lpt][epl]: (edge id) | (src gene << 16), or -1 for an empty slot.
+    std::vector<int32_t> lane_edge;
+    // [N]: row lane | (first prefix index << 8) | (end prefix index << 16).
+    std::vector<int32_t> gene_row;
+};
+
+struct DevicePlan {
+    int device = -1;
+    int lpt = 0;
+    int32_t* lane_edge = nullptr;  // [lpt][stride]
+    int32_t* gene_row = nullptr;   // [N]
+    int32_t* row_ptr = nullptr;    // [N + 1]
+    int8_t* sign = nullptr;        // [E]
+    void* block = nullptr;         // single allocation holding the above
+};
+
+}  // namespace rac
+
+struct rac_topology {
+    int32_t n_genes = 0;
+    int32_t n_edges = 0;
+    std::vector<int32_t> src, dst;   // canonical (dst, src) order
+    std::vector<int8_t> sign;
+    std::vector<int32_t> row_ptr;    // [N + 1] CSR by target
+    mutable std::mutex mu;
+    // Deques keep element addresses stable while new plans are appended.
+    mutable std::deque<rac::LanePlan> plans;        // by lpt, built lazily
+    mutable std::deque<rac::DevicePlan> dev_plans;  // by (device, lpt)
+};
+
+namespace rac {
+
+void set_error(const std::string& msg);
+rac_status fail(rac_status st, const std::string& msg);
+
+// Host-side lane plan (built once per (topology, lpt), cached).
+const LanePlan* get_plan(const rac_topology* t, int lpt);
+int max_in_degree(const rac_topology* t);
+// Cheapest compiled shape covering (epl, gpl); {0, 0} if none.
+Shape pick_shape(int epl, int gpl, int precision);
+bool plan_fits(const rac_topology* t, int lpt, int precision);
+int auto_lanes(const rac_topology* t, int precision);
+
+// Device copy of a plan on the current device (cached in the handle).
+rac_status get_device_plan(const rac_topology* t, int lpt, const DevicePlan** out);
+void free_device_plans(rac_topology* t);
+
+}  // namespace rac

@@ -1,0 +1,376 @@
+// Host side of the integration calls: option checks, device copies of the
+// lane plans, kernel selection, persistent-grid sizing and launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "kernel_table.h"
+#include "rac_internal.h"
+
+namespace rac {
+
+#define RAC_HIP(call, what)                                                             \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(RAC_EDEVICE, std::string(what) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+const KernelEntry* find_kernel(int precision, bool ts, int epl, int gpl) {
+    static std::vector<KernelEntry> all = [] {
+        std::vector<KernelEntry> v;
+        for (auto fn : {kernels_f32_ss, kernels_f32_ts, kernels_f64_ss, kernels_f64_ts}) {
+            const KernelEntry* t = nullptr;
+            int n = fn(&t);
+            v.insert(v.end(), t, t + n);
+        }
+        return v;
+    }();
+    for (const KernelEntry& k : all)
+        if (k.precision == precision && k.ts == ts && k.epl == epl && k.gpl == gpl) return &k;
+    return nullptr;
+}
+
+rac_status get_device_plan(const rac_topology* t, int lpt, const DevicePlan** out) {
+    int dev = 0;
+    RAC_HIP(hipGetDevice(&dev), "hipGetDevice");
+    const LanePlan* lp = get_plan(t, lpt);
+    std::lock_guard<std::mutex> lk(t->mu);
+    for (auto& d : t->dev_plans)
+        if (d.device == dev && d.lpt == lpt) {
+            *out = &d;
+            return RAC_OK;
+        }
+    const size_t n_le = lp->lane_edge.size(), N = t->n_genes, E = t->n_edges;
+    const size_t bytes = 4 * (n_le + N + N + 1) + std::max<size_t>(E, 1);
+    void* block = nullptr;
+    if (hipMalloc(&block, bytes) != hipSuccess)
+        return fail(RAC_ENOMEM, "device plan: hipMalloc failed");
+    std::vector<char> host(bytes, 0);
+    char* h = host.data();
+    std::memcpy(h, lp->lane_edge.data(), 4 * n_le);
+    std::memcpy(h + 4 * n_le, lp->gene_row.data(), 4 * N);
+    std::memcpy(h + 4 * (n_le + N), t->row_ptr.data(), 4 * (N + 1));
+    if (E) std::memcpy(h + 4 * (n_le + 2 * N + 1), t->sign.data(), E);
+    if (hipMemcpy(block, h, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(block);
+        return fail(RAC_EDEVICE, "device plan: hipMemcpy failed");
+    }
+    DevicePlan d;
+    d.device = dev;
+    d.lpt = lpt;
+    d.block = block;
+    char* b = (char*)block;
+    d.lane_edge = (int32_t*)b;
+    d.gene_row = (int32_t*)(b + 4 * n_le);
+    d.row_ptr = (int32_t*)(b + 4 * (n_le + N));
+    d.sign = (int8_t*)(b + 4 * (n_le + 2 * N + 1));
+    t->dev_plans.push_back(d);
+    *out = &t->dev_plans.back();
+    return RAC_OK;
+}
+
+void free_device_plans(rac_topology* t) {
+    int cur = 0;
+    bool have_cur = hipGetDevice(&cur) == hipSuccess;
+    for (auto& d : t->dev_plans) {
+        if (hipSetDevice(d.device) == hipSuccess) (void)hipFree(d.block);
+    }
+    if (have_cur) (void)hipSetDevice(cur);
+    t->dev_plans.clear();
+}
+
+namespace {
+
+// Zero the queue counter with a kernel (no memset node in captured graphs).
+__global__ void zero_counter(unsigned long long* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0ull;
+}
+
+rac_status check_opts(const rac_solver_opts* o, const char* who) {
+    std::string w(who);
+    if (!o) return fail(RAC_EINVAL, w + ": NULL opts");
+    if (o->precision != RAC_FP32 && o->precision != RAC_FP64)
+        return fail(RAC_EINVAL, w + ": precision must be RAC_FP32 or RAC_FP64");
+    if (!std::isfinite(o->t0) || !std::isfinite(o->t_end))
+        return fail(RAC_EINVAL, w + ": t0 and t_end must be finite");
+    if (!(o->rtol >= 0) || !(o->atol >= 0) || !(o->rtol + o->atol > 0))
+        return fail(RAC_EINVAL, w + ": need rtol >= 0, atol >= 0, rtol + atol > 0");
+    if (!(o->ss_atol >= 0) || !(o->ss_rtol >= 0))
+        return fail(RAC_EINVAL, w + ": steady tolerances must be >= 0");
+    if (o->max_steps < 1) return fail(RAC_EINVAL, w + ": max_steps < 1");
+    if (!(o->h0 <= 0 || std::isfinite(o->h0))) return fail(RAC_EINVAL, w + ": h0 not finite");
+    if (o->lanes_per_traj < 0 || o->lanes_per_traj > kWave ||
+        (o->lanes_per_traj & (o->lanes_per_traj - 1)))
+        return fail(RAC_EINVAL, w + ": lanes_per_traj must be 0 or a power of two <= 64");
+    if (o->refill_min < 0) return fail(RAC_EINVAL, w + ": refill_min < 0");
+    return RAC_OK;
+}
+
+rac_status check_item(const rac_topology* topo, const rac_params_view* p, const float* ic,
+                      int32_t n_ic, const void* x_out, const char* who) {
+    std::string w(who);
+    if (!topo) return fail(RAC_EINVAL, w + ": NULL topology");
+    if (!p) return fail(RAC_EINVAL, w + ": NULL params");
+    if (p->n_sets < 0) return fail(RAC_EINVAL, w + ": n_sets < 0");
+    if (n_ic < 1) return fail(RAC_EINVAL, w + ": n_ic < 1");
+    if (p->n_sets > 0) {
+        if (!p->G || !p->k || (topo->n_edges > 0 && (!p->T || !p->lam || !p->n)))
+            return fail(RAC_EINVAL, w + ": NULL parameter array");
+        if (!ic) return fail(RAC_EINVAL, w + ": NULL initial conditions");
+        if (!x_out) return fail(RAC_EINVAL, w + ": NULL x_out");
+        if (p->n_sets > (int64_t)1 << 40) return fail(RAC_EUNSUPPORTED, w + ": n_sets too large");
+    }
+    return RAC_OK;
+}
+
+struct Job {
+    const rac_topology* topo;
+    rac_params_view params;
+    const float* ic;
+    int32_t n_ic;
+    void* x_out;
+    rac_traj_info info;
+};
+
+int pick_lanes(const rac_topology* t, const rac_solver_opts* o) {
+    return o->lanes_per_traj > 0 ? o->lanes_per_traj : auto_lanes(t, o->precision);
+}
+
+Controls make_controls(const rac_solver_opts* o, int n_groups) {
+    Controls c;
+    c.t0 = o->t0;
+    c.t_end = o->t_end;
+    c.rtol = o->rtol;
+    c.atol = o->atol;
+    c.ss_atol = o->ss_atol;
+    c.ss_rtol = o->ss_rtol;
+    c.h0 = o->h0;
+    c.max_steps = o->max_steps;
+    c.divide = o->activation_divides_by_lambda ? 1 : 0;
+    c.ic_absolute = o->ic_absolute ? 1 : 0;
+    c.stop_at_steady = o->stop_at_steady ? 1 : 0;
+    c.refill_min = o->refill_min > 0 ? o->refill_min : std::max(1, n_groups / 4);
+    return c;
+}
+
+std::map<std::tuple<int, const void*>, int>& occupancy_cache() {
+    static std::map<std::tuple<int, const void*>, int> m;
+    return m;
+}
+
+// Launch one persistent kernel over the given networks (all with lane count
+// lpt) in a shared work queue.
+rac_status launch_group(const std::vector<Job>& jobs, int lpt, const rac_solver_opts* o, bool ts,
+                        const double* host_t_out, int32_t n_t, hipStream_t stream) {
+    int epl = 0, gpl = 0, max_n = 0;
+    int64_t total = 0;
+    std::vector<NetDesc> descs;
+    for (const Job& j : jobs) {
+        const LanePlan* lp = get_plan(j.topo, lpt);
+        const DevicePlan* dp = nullptr;
+        rac_status st = get_device_plan(j.topo, lpt, &dp);
+        if (st != RAC_OK) return st;
+        NetDesc d;
+        d.lane_edge = dp->lane_edge;
+        d.gene_row = dp->gene_row;
+        d.row_ptr = dp->row_ptr;
+        d.sign = dp->sign;
+        d.G = j.params.G;
+        d.k = j.params.k;
+        d.T = j.params.T;
+        d.lam = j.params.lam;
+        d.n = j.params.n;
+        d.ic = j.ic;
+        d.x_out = j.x_out;
+        d.t_final = j.info.t_final;
+        d.status = j.info.status;
+        d.n_acc = j.info.n_accepted;
+        d.n_rej = j.info.n_rejected;
+        d.n_sets = j.params.n_sets;
+        d.traj_begin = total;
+        d.n_traj = j.params.n_sets * j.n_ic;
+        d.n_genes = j.topo->n_genes;
+        d.n_edges = j.topo->n_edges;
+        d.n_ic = j.n_ic;
+        d.inv_n_ic = 1.0 / j.n_ic;
+        d.stride = lp->stride;
+        total += d.n_traj;
+        epl = std::max(epl, lp->epl);
+        gpl = std::max(gpl, lp->gpl);
+        max_n = std::max(max_n, j.topo->n_genes);
+        descs.push_back(d);
+    }
+    if (total == 0) return RAC_OK;
+    const Shape shape = pick_shape(std::max(epl, 1), gpl, o->precision);
+    const KernelEntry* ke = shape.epl ? find_kernel(o->precision, ts, shape.epl, shape.gpl) : nullptr;
+    if (!ke) return fail(RAC_EUNSUPPORTED, "no compiled kernel for this network size and lane count");
+
+    int dev = 0, n_cu = 0;
+    RAC_HIP(hipGetDevice(&dev), "hipGetDevice");
+    RAC_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+    int per_cu = 0;
+    {
+        static std::mutex m;
+        std::lock_guard<std::mutex> lk(m);
+        auto key = std::make_tuple(dev, ke->fn);
+        auto it = occupancy_cache().find(key);
+        if (it == occupancy_cache().end()) {
+            RAC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ke->fn, kBlock, 0),
+                    "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+            occupancy_cache()[key] = per_cu;
+        } else {
+            per_cu = it->second;
+        }
+    }
+    per_cu = std::max(per_cu, 1);
+    const int n_groups = kWave / lpt;
+    const int64_t waves_needed = (total + n_groups - 1) / n_groups;
+    const int64_t blocks_needed = (waves_needed + kBlock / kWave - 1) / (kBlock / kWave);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)per_cu * n_cu, blocks_needed));
+
+    LaunchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.n_nets = (int32_t)descs.size();
+    a.total = total;
+    a.lpt = lpt;
+    a.epl = epl;
+    a.gpl = gpl;
+    a.n_t = ts ? n_t : 0;
+    a.c = make_controls(o, n_groups);
+
+    // Per-call device block: queue counter, network table, output times.
+    const size_t off_nets = 256;
+    const size_t off_t = off_nets + (descs.size() > 1 ? descs.size() * sizeof(NetDesc) : 0);
+    const size_t bytes = off_t + (ts ? sizeof(double) * n_t : 0);
+    void* blk = nullptr;
+    RAC_HIP(hipMallocAsync(&blk, bytes, stream), "hipMallocAsync");
+    char* b = (char*)blk;
+    a.counter = (unsigned long long*)b;
+    if (descs.size() > 1) {
+        a.nets = (const NetDesc*)(b + off_nets);
+        RAC_HIP(hipMemcpyAsync(b + off_nets, descs.data(), descs.size() * sizeof(NetDesc),
+                               hipMemcpyHostToDevice, stream), "hipMemcpyAsync(nets)");
+    } else {
+        a.nets = nullptr;
+        a.net0 = descs[0];
+    }
+    if (ts) {
+        a.t_out = (const double*)(b + off_t);
+        RAC_HIP(hipMemcpyAsync(b + off_t, host_t_out, sizeof(double) * n_t, hipMemcpyHostToDevice, stream),
+                "hipMemcpyAsync(t_out)");
+    }
+    hipLaunchKernelGGL(zero_counter, dim3(1), dim3(64), 0, stream, a.counter);
+    RAC_HIP(hipGetLastError(), "zero_counter launch");
+    void* args[] = {&a};
+    RAC_HIP(hipLaunchKernel(ke->fn, dim3(grid), dim3(kBlock), args, 0, stream), "dp5 kernel launch");
+    RAC_HIP(hipFreeAsync(blk, stream), "hipFreeAsync");
+    return RAC_OK;
+}
+
+rac_status run_jobs(std::vector<Job>& jobs, const rac_solver_opts* o, bool ts,
+                    const double* host_t_out, int32_t n_t, void* stream) {
+    // Group networks by (lane count, kernel shape): one persistent launch each.
+    std::map<std::tuple<int, int, int>, std::vector<Job>> groups;
+    for (const Job& j : jobs) {
+        if (j.params.n_sets == 0) continue;
+        const int lpt = pick_lanes(j.topo, o);
+        if (lpt == 0 || !plan_fits(j.topo, lpt, o->precision))
+            return fail(RAC_EUNSUPPORTED, "network (N=" + std::to_string(j.topo->n_genes) + ", E=" +
+                                              std::to_string(j.topo->n_edges) +
+                                              ") does not fit the compiled kernels at this lane count");
+        const LanePlan* lp = get_plan(j.topo, lpt);
+        const Shape s = pick_shape(std::max(lp->epl, 1), lp->gpl, o->precision);
+        groups[std::make_tuple(lpt, s.epl, s.gpl)].push_back(j);
+    }
+    for (auto& kv : groups) {
+        rac_status st = launch_group(kv.second, std::get<0>(kv.first), o, ts, host_t_out, n_t,
+                                     (hipStream_t)stream);
+        if (st != RAC_OK) return st;
+    }
+    return RAC_OK;
+}
+
+}  // namespace
+}  // namespace rac
+
+extern "C" {
+
+void rac_default_opts(rac_solver_opts* o, int32_t precision) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->t0 = 0.0;
+    o->t_end = 200.0;
+    o->rtol = 1e-6;
+    o->atol = 1e-9;
+    o->ss_atol = 1e-6;
+    o->ss_rtol = precision == RAC_FP64 ? 0.0 : 1e-5;
+    o->h0 = 0.0;
+    o->max_steps = 100000;
+    o->precision = precision;
+    o->activation_divides_by_lambda = 1;
+    o->stop_at_steady = 0;
+    o->ic_absolute = 0;
+    o->lanes_per_traj = 0;
+    o->refill_min = 0;
+}
+
+rac_status rac_steady_states(const rac_topology* topo, const rac_params_view* dev_params,
+                             const float* dev_ic, int32_t n_ic, const rac_solver_opts* opts,
+                             void* dev_x_out, const rac_traj_info* dev_info, void* hip_stream) {
+    using namespace rac;
+    rac_status st = check_opts(opts, "rac_steady_states");
+    if (st != RAC_OK) return st;
+    if (!(opts->t_end > opts->t0)) return fail(RAC_EINVAL, "rac_steady_states: t_end <= t0");
+    st = check_item(topo, dev_params, dev_ic, n_ic, dev_x_out, "rac_steady_states");
+    if (st != RAC_OK) return st;
+    std::vector<Job> jobs{{topo, *dev_params, dev_ic, n_ic, dev_x_out,
+                           dev_info ? *dev_info : rac_traj_info{nullptr, nullptr, nullptr, nullptr}}};
+    return run_jobs(jobs, opts, false, nullptr, 0, hip_stream);
+}
+
+rac_status rac_integrate(const rac_topology* topo, const rac_params_view* dev_params,
+                         const float* dev_ic, int32_t n_ic, const rac_solver_opts* opts,
+                         const double* host_t_out, int32_t n_t, void* dev_x_out,
+                         const rac_traj_info* dev_info, void* hip_stream) {
+    using namespace rac;
+    rac_status st = check_opts(opts, "rac_integrate");
+    if (st != RAC_OK) return st;
+    st = check_item(topo, dev_params, dev_ic, n_ic, dev_x_out, "rac_integrate");
+    if (st != RAC_OK) return st;
+    if (n_t < 1 || !host_t_out) return fail(RAC_EINVAL, "rac_integrate: need n_t >= 1 output times");
+    for (int i = 0; i < n_t; ++i) {
+        if (!std::isfinite(host_t_out[i]) || host_t_out[i] < opts->t0)
+            return fail(RAC_EINVAL, "rac_integrate: output time before t0 or not finite");
+        if (i > 0 && !(host_t_out[i] > host_t_out[i - 1]))
+            return fail(RAC_EINVAL, "rac_integrate: output times must be strictly increasing");
+    }
+    std::vector<Job> jobs{{topo, *dev_params, dev_ic, n_ic, dev_x_out,
+                           dev_info ? *dev_info : rac_traj_info{nullptr, nullptr, nullptr, nullptr}}};
+    return run_jobs(jobs, opts, true, host_t_out, n_t, hip_stream);
+}
+
+rac_status rac_steady_states_batch(const rac_batch_item* items, int32_t n_items,
+                                   const rac_solver_opts* opts, void* hip_stream) {
+    using namespace rac;
+    rac_status st = check_opts(opts, "rac_steady_states_batch");
+    if (st != RAC_OK) return st;
+    if (!(opts->t_end > opts->t0)) return fail(RAC_EINVAL, "rac_steady_states_batch: t_end <= t0");
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(RAC_EINVAL, "rac_steady_states_batch: bad items");
+    std::vector<Job> jobs;
+    for (int i = 0; i < n_items; ++i) {
+        const rac_batch_item& it = items[i];
+        st = check_item(it.topo, &it.params, it.ic, it.n_ic, it.x_out, "rac_steady_states_batch");
+        if (st != RAC_OK) return st;
+        jobs.push_back({it.topo, it.params, it.ic, it.n_ic, it.x_out, it.info});
+    }
+    return run_jobs(jobs, opts, false, nullptr, 0, hip_stream);
+}
+
+}  // extern "C"

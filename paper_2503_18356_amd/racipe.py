@@ -1,0 +1,342 @@
+"""Python binding of librac.so (the C ABI in include/rac.h).
+
+Argument marshalling only: every step of the integration runs in the HIP
+kernels behind the C ABI.  PyTorch provides device memory and streams.  The
+binding fails loudly when the native library is missing; there is no CPU
+fallback.
+
+Names follow rac.h: ``create_topology``, ``sample_params``, ``steady_states``,
+``integrate`` and ``steady_states_batch``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, fields
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librac.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
+CONVERGED, T_END, MAX_STEPS, STEP_UNDERFLOW, NONFINITE = range(5)
+FP32, FP64 = 0, 1
+STATUS_NAMES = ["CONVERGED", "T_END", "MAX_STEPS", "STEP_UNDERFLOW", "NONFINITE"]
+
+
+class RacError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"rac error {code}: {msg}")
+        self.code = code
+
+
+class _Ranges(C.Structure):
+    _fields_ = [("g_min", C.c_double), ("g_max", C.c_double), ("k_min", C.c_double),
+                ("k_max", C.c_double), ("lam_act_min", C.c_double), ("lam_act_max", C.c_double),
+                ("lam_inh_min", C.c_double), ("lam_inh_max", C.c_double), ("n_min", C.c_int32),
+                ("n_max", C.c_int32), ("t_lo", C.c_double), ("t_hi", C.c_double),
+                ("t_median", C.c_double)]
+
+
+class _ParamsView(C.Structure):
+    _fields_ = [("G", C.c_void_p), ("k", C.c_void_p), ("T", C.c_void_p), ("lam", C.c_void_p),
+                ("n", C.c_void_p), ("n_sets", C.c_int64)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("t0", C.c_double), ("t_end", C.c_double), ("rtol", C.c_double),
+                ("atol", C.c_double), ("ss_atol", C.c_double), ("ss_rtol", C.c_double),
+                ("h0", C.c_double), ("max_steps", C.c_int64), ("precision", C.c_int32),
+                ("activation_divides_by_lambda", C.c_int32), ("stop_at_steady", C.c_int32),
+                ("ic_absolute", C.c_int32), ("lanes_per_traj", C.c_int32),
+                ("refill_min", C.c_int32)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("t_final", C.c_void_p), ("status", C.c_void_p), ("n_accepted", C.c_void_p),
+                ("n_rejected", C.c_void_p)]
+
+
+class _BatchItem(C.Structure):
+    _fields_ = [("topo", C.c_void_p), ("params", _ParamsView), ("ic", C.c_void_p),
+                ("n_ic", C.c_int32), ("x_out", C.c_void_p), ("info", _Info)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded librac.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.rac_last_error.restype = C.c_char_p
+        L.rac_version.restype = C.c_char_p
+        L.rac_create_topology.argtypes = [i32, i32, vp, vp, vp, C.POINTER(vp)]
+        L.rac_create_topology.restype = C.c_int
+        L.rac_destroy_topology.argtypes = [vp]
+        L.rac_topology_size.argtypes = [vp, vp, vp]
+        L.rac_topology_size.restype = C.c_int
+        L.rac_topology_edges.argtypes = [vp, vp, vp, vp]
+        L.rac_topology_edges.restype = C.c_int
+        L.rac_default_ranges.argtypes = [C.POINTER(_Ranges)]
+        L.rac_sample_params.argtypes = [vp, C.POINTER(_Ranges), C.c_uint64, i64, i64, i32,
+                                        C.POINTER(_ParamsView), vp]
+        L.rac_sample_params.restype = C.c_int
+        L.rac_default_opts.argtypes = [C.POINTER(_Opts), i32]
+        L.rac_steady_states.argtypes = [vp, C.POINTER(_ParamsView), vp, i32, C.POINTER(_Opts),
+                                        vp, C.POINTER(_Info), vp]
+        L.rac_steady_states.restype = C.c_int
+        L.rac_integrate.argtypes = [vp, C.POINTER(_ParamsView), vp, i32, C.POINTER(_Opts), vp,
+                                    i32, vp, C.POINTER(_Info), vp]
+        L.rac_integrate.restype = C.c_int
+        L.rac_steady_states_batch.argtypes = [C.POINTER(_BatchItem), i32, C.POINTER(_Opts), vp]
+        L.rac_steady_states_batch.restype = C.c_int
+        L.rac_auto_lanes.argtypes = [vp, i32]
+        L.rac_auto_lanes.restype = i32
+        L.rac_lanes_supported.argtypes = [vp, i32, i32]
+        L.rac_lanes_supported.restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != OK:
+        raise RacError(code, lib().rac_last_error().decode())
+
+
+def last_error() -> str:
+    return lib().rac_last_error().decode()
+
+
+class Topology:
+    """Owns a rac_topology handle; edges are kept in canonical (dst, src) order."""
+
+    def __init__(self, n_genes: int, src, dst, sign):
+        s = np.ascontiguousarray(src, dtype=np.int32)
+        d = np.ascontiguousarray(dst, dtype=np.int32)
+        g = np.ascontiguousarray(sign, dtype=np.int8)
+        h = C.c_void_p()
+        _check(lib().rac_create_topology(int(n_genes), int(s.size), s.ctypes.data, d.ctypes.data,
+                                         g.ctypes.data, C.byref(h)))
+        self._h = h
+        self.n_genes = int(n_genes)
+        self.n_edges = int(s.size)
+        self.src = np.zeros(self.n_edges, np.int32)
+        self.dst = np.zeros(self.n_edges, np.int32)
+        self.sign = np.zeros(self.n_edges, np.int8)
+        _check(lib().rac_topology_edges(h, self.src.ctypes.data, self.dst.ctypes.data,
+                                        self.sign.ctypes.data))
+
+    @classmethod
+    def from_inputs(cls, t) -> "Topology":
+        return cls(t.n_genes, t.src, t.dst, t.sign)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def auto_lanes(self, precision: int = FP32) -> int:
+        return int(lib().rac_auto_lanes(self._h, precision))
+
+    def lanes_supported(self, lanes: int, precision: int = FP32) -> bool:
+        return bool(lib().rac_lanes_supported(self._h, precision, lanes))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.rac_destroy_topology(h)
+            self._h = None
+
+
+def create_topology(n_genes: int, src, dst, sign) -> Topology:
+    return Topology(n_genes, src, dst, sign)
+
+
+@dataclass
+class Ranges:
+    g_min: float = 1.0
+    g_max: float = 100.0
+    k_min: float = 0.1
+    k_max: float = 1.0
+    lam_act_min: float = 1.0
+    lam_act_max: float = 100.0
+    lam_inh_min: float = 0.01
+    lam_inh_max: float = 1.0
+    n_min: int = 1
+    n_max: int = 6
+    t_lo: float = 0.02
+    t_hi: float = 1.98
+    t_median: float = 0.0
+
+    def c(self) -> _Ranges:
+        return _Ranges(*[getattr(self, f[0]) for f in _Ranges._fields_])
+
+
+@dataclass
+class HostParams:
+    """Host arrays in the layout of rac_params_view (set index fastest)."""
+    G: np.ndarray
+    k: np.ndarray
+    T: np.ndarray
+    lam: np.ndarray
+    n: np.ndarray
+    ic: np.ndarray
+
+    @property
+    def n_sets(self) -> int:
+        return int(self.G.shape[1])
+
+    def to_device(self, device="cuda"):
+        import torch
+        return DeviceParams(*[torch.from_numpy(np.ascontiguousarray(getattr(self, f.name))).to(device)
+                              for f in fields(self)])
+
+
+@dataclass
+class DeviceParams:
+    """torch tensors on the GPU: G, k [N][P]; T, lam [E][P] f32; n [E][P] u8; ic [n_ic][N]."""
+    G: object
+    k: object
+    T: object
+    lam: object
+    n: object
+    ic: object
+
+    @property
+    def n_sets(self) -> int:
+        return int(self.G.shape[1])
+
+    @property
+    def n_ic(self) -> int:
+        return int(self.ic.shape[0])
+
+    def view(self) -> _ParamsView:
+        return _ParamsView(self.G.data_ptr(), self.k.data_ptr(), self.T.data_ptr(),
+                           self.lam.data_ptr(), self.n.data_ptr(), self.n_sets)
+
+
+def sample_params(topo: Topology, seed: int, n_sets: int, n_ic: int, set_begin: int = 0,
+                  ranges: Ranges | None = None) -> HostParams:
+    N, E, P = topo.n_genes, topo.n_edges, int(n_sets)
+    G = np.zeros((N, P), np.float32)
+    k = np.zeros((N, P), np.float32)
+    T = np.zeros((E, P), np.float32)
+    lam = np.zeros((E, P), np.float32)
+    n = np.zeros((E, P), np.uint8)
+    ic = np.zeros((n_ic, N), np.float32)
+    v = _ParamsView(G.ctypes.data, k.ctypes.data, T.ctypes.data, lam.ctypes.data, n.ctypes.data, P)
+    rr = (ranges or Ranges()).c()
+    _check(lib().rac_sample_params(topo.handle, C.byref(rr), C.c_uint64(seed & (2**64 - 1)),
+                                   set_begin, P, n_ic, C.byref(v), ic.ctypes.data))
+    return HostParams(G, k, T, lam, n, ic)
+
+
+@dataclass
+class Opts:
+    t0: float = 0.0
+    t_end: float = 200.0
+    rtol: float = 1e-6
+    atol: float = 1e-9
+    ss_atol: float = 1e-6
+    ss_rtol: float | None = None   # None: 1e-5 for FP32, 0 for FP64
+    h0: float = 0.0
+    max_steps: int = 100000
+    precision: int = FP32
+    activation_divides_by_lambda: int = 1
+    stop_at_steady: int = 0
+    ic_absolute: int = 0
+    lanes_per_traj: int = 0
+    refill_min: int = 0
+
+    def c(self) -> _Opts:
+        o = _Opts()
+        lib().rac_default_opts(C.byref(o), self.precision)
+        for f in fields(self):
+            v = getattr(self, f.name)
+            if v is not None:
+                setattr(o, f.name, v)
+        return o
+
+
+@dataclass
+class Result:
+    x: object          # torch tensor [n_traj][N] (or [n_traj][n_t][N])
+    t_final: object    # f64 [n_traj]
+    status: object     # i8 [n_traj]
+    n_acc: object      # i32 [n_traj]
+    n_rej: object      # i32 [n_traj]
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def alloc_result(n_traj: int, n_genes: int, precision: int, n_t: int = 0, device="cuda") -> Result:
+    import torch
+    dt = torch.float32 if precision == FP32 else torch.float64
+    shape = (n_traj, n_t, n_genes) if n_t else (n_traj, n_genes)
+    return Result(torch.empty(shape, dtype=dt, device=device),
+                  torch.empty(n_traj, dtype=torch.float64, device=device),
+                  torch.empty(n_traj, dtype=torch.int8, device=device),
+                  torch.empty(n_traj, dtype=torch.int32, device=device),
+                  torch.empty(n_traj, dtype=torch.int32, device=device))
+
+
+def _info(res: Result) -> _Info:
+    return _Info(res.t_final.data_ptr(), res.status.data_ptr(), res.n_acc.data_ptr(),
+                 res.n_rej.data_ptr())
+
+
+def steady_states(topo: Topology, params: DeviceParams, opts: Opts | None = None,
+                  out: Result | None = None, stream=None) -> Result:
+    """Enqueue rac_steady_states on the stream (asynchronous)."""
+    opts = opts or Opts()
+    n_traj = params.n_sets * params.n_ic
+    out = out or alloc_result(n_traj, topo.n_genes, opts.precision, device=params.G.device)
+    v = params.view()
+    info = _info(out)
+    o = opts.c()
+    _check(lib().rac_steady_states(topo.handle, C.byref(v), params.ic.data_ptr(), params.n_ic,
+                                   C.byref(o), out.x.data_ptr(), C.byref(info), _stream_ptr(stream)))
+    return out
+
+
+def integrate(topo: Topology, params: DeviceParams, t_out, opts: Opts | None = None,
+              out: Result | None = None, stream=None) -> Result:
+    """Enqueue rac_integrate (time series at t_out) on the stream."""
+    opts = opts or Opts()
+    t = np.ascontiguousarray(t_out, dtype=np.float64)
+    n_traj = params.n_sets * params.n_ic
+    out = out or alloc_result(n_traj, topo.n_genes, opts.precision, n_t=t.size,
+                              device=params.G.device)
+    v = params.view()
+    info = _info(out)
+    o = opts.c()
+    _check(lib().rac_integrate(topo.handle, C.byref(v), params.ic.data_ptr(), params.n_ic,
+                               C.byref(o), t.ctypes.data, int(t.size), out.x.data_ptr(),
+                               C.byref(info), _stream_ptr(stream)))
+    return out
+
+
+def steady_states_batch(items, opts: Opts | None = None, stream=None) -> list[Result]:
+    """items: list of (Topology, DeviceParams[, Result]).  One fused launch per
+    kernel shape; returns the Results."""
+    opts = opts or Opts()
+    outs, arr = [], (_BatchItem * max(len(items), 1))()
+    for i, it in enumerate(items):
+        topo, prm = it[0], it[1]
+        out = it[2] if len(it) > 2 and it[2] is not None else alloc_result(
+            prm.n_sets * prm.n_ic, topo.n_genes, opts.precision, device=prm.G.device)
+        outs.append(out)
+        arr[i] = _BatchItem(topo.handle.value, prm.view(), prm.ic.data_ptr(), prm.n_ic,
+                            out.x.data_ptr(), _info(out))
+    o = opts.c()
+    _check(lib().rac_steady_states_batch(arr, len(items), C.byref(o), _stream_ptr(stream)))
+    return outs

@@ -1,0 +1,121 @@
+"""GPU-vs-oracle comparison helpers.
+
+Metric: per component, the error normalised by the gene's maximal level,
+|x_gpu - x_ref| / (G_i / k_i) (GRiNS compares states only after G/k
+normalisation, Sec. 2.1.3), must be <= 1e-4.
+
+Several results can be correct for a multistable system (Sec. 3.1), so two
+kinds of disagreement are adjudicated rather than failed outright:
+  - basin flip: some normalised component differs by more than 0.5.  It is
+    excused when the oracle itself lands in another basin from x0 * (1 +- 1e-5),
+    i.e. the start sits on a separatrix at that resolution;
+  - slow manifold: |dx_i| <= (|f_gpu,i| + |f_ref,i|) / |lambda_min(J(x_ref))|,
+    i.e. both results are within their own residual of the same slow fixed point.
+Unexcused disagreements must be zero and flips at most 0.1 % of the sample.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+import oracle
+
+TOL = 1e-4
+
+
+def gk_of(prm, traj, n_ic):
+    p = np.asarray(traj) // n_ic
+    return (prm.G[:, p] / prm.k[:, p]).T.astype(np.float64)  # [n][N]
+
+
+def _jac_min_eig(net, prm, p, x):
+    N = x.size
+    J = np.zeros((N, N))
+    for j in range(N):
+        d = 1e-6 * max(1.0, abs(x[j]))
+        xp = x.copy(); xp[j] += d
+        xm = x.copy(); xm[j] -= d
+        J[:, j] = (oracle.rhs(net, prm, p, xp) - oracle.rhs(net, prm, p, xm)) / (2 * d)
+    ev = np.linalg.eigvals(J)
+    return float(np.min(np.abs(ev.real)))
+
+
+def _single(prm, p, c, scale=1.0):
+    """Parameter set p and initial condition c as a one-trajectory problem."""
+    return oracle.Params(prm.G[:, p:p + 1].copy(), prm.k[:, p:p + 1].copy(),
+                         prm.T[:, p:p + 1].copy(), prm.lam[:, p:p + 1].copy(),
+                         prm.n[:, p:p + 1].copy(),
+                         (prm.ic[c:c + 1] * np.float32(scale)).astype(np.float32))
+
+
+@dataclass
+class Report:
+    n: int
+    max_err: float
+    p50_rel: float
+    p99_rel: float
+    max_rel: float
+    flips: int
+    excused_flips: int
+    slow: int
+    unexcused: list
+
+    def ok(self) -> bool:
+        return not self.unexcused and self.flips <= max(1, int(0.001 * self.n))
+
+    def __str__(self):
+        return (f"n={self.n} max_norm_err={self.max_err:.2e} rel p50/p99/max="
+                f"{self.p50_rel:.1e}/{self.p99_rel:.1e}/{self.max_rel:.1e} flips={self.flips} "
+                f"(excused {self.excused_flips}) slow={self.slow} unexcused={len(self.unexcused)}")
+
+
+def compare_steady(net, prm, opts, traj, x_gpu, x_ref, n_ic, adjudicate=True) -> Report:
+    """x_gpu, x_ref: [n][N] for trajectories `traj` (ids p * n_ic + c)."""
+    x_gpu = np.asarray(x_gpu, np.float64)
+    x_ref = np.asarray(x_ref, np.float64)
+    gk = gk_of(prm, traj, n_ic)
+    err = np.abs(x_gpu - x_ref) / gk
+    rel = np.abs(x_gpu - x_ref) / np.maximum(np.abs(x_ref), 1e-12)
+    bad = np.flatnonzero(err.max(axis=1) > TOL)
+    flips = excused_flips = slow = 0
+    unexcused = []
+    for i in bad:
+        t = int(traj[i])
+        p, c = divmod(t, n_ic)
+        if not adjudicate:
+            unexcused.append((t, float(err[i].max())))
+            continue
+        if err[i].max() > 0.5:
+            flips += 1
+            moved = False
+            for sc in (1 + 1e-5, 1 - 1e-5):
+                r = oracle.steady_states(net, _single(prm, p, c, sc), opts, n_threads=1)
+                if np.max(np.abs(r.x[0] - x_ref[i]) / gk[i]) > 0.5:
+                    moved = True
+            if moved:
+                excused_flips += 1
+            else:
+                unexcused.append((t, float(err[i].max()), "flip"))
+            continue
+        sp = _single(prm, p, c)
+        f_gpu = oracle.rhs(net, sp, 0, x_gpu[i])
+        f_ref = oracle.rhs(net, sp, 0, x_ref[i])
+        lam = _jac_min_eig(net, sp, 0, x_ref[i])
+        bound = (np.abs(f_gpu) + np.abs(f_ref)) / max(lam, 1e-300)
+        if np.all(np.abs(x_gpu[i] - x_ref[i]) <= bound + TOL * gk[i]):
+            slow += 1
+        else:
+            unexcused.append((t, float(err[i].max()), "slow-bound", float(lam)))
+    return Report(len(traj), float(err.max()) if err.size else 0.0,
+                  float(np.percentile(rel, 50)) if rel.size else 0.0,
+                  float(np.percentile(rel, 99)) if rel.size else 0.0,
+                  float(rel.max()) if rel.size else 0.0, flips, excused_flips, slow, unexcused)
+
+
+def compare_series(prm, traj, x_gpu, x_ref, n_ic):
+    """Per output time: max normalised error and max relative error."""
+    gk = gk_of(prm, traj, n_ic)[:, None, :]
+    err = np.abs(np.asarray(x_gpu, np.float64) - x_ref) / gk
+    rel = np.abs(np.asarray(x_gpu, np.float64) - x_ref) / np.maximum(np.abs(x_ref), 1e-12)
+    return err.max(axis=(0, 2)), rel.max(axis=(0, 2))

@@ -1,0 +1,160 @@
+"""CPU checks of the C ABI: exported symbols, topology validation, the host
+sampler (bit-exact against the oracle's independent sampler), and argument
+errors that integration calls report before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_18356_amd import inputs
+from paper_2503_18356_amd import racipe as rp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    with open(os.path.join(ROOT, "include", "rac.h")) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rac_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert "rac_steady_states" in names and "rac_integrate" in names
+    assert "rac_create_topology" in names and "rac_sample_params" in names
+    L = rp.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def _topo(n, src, dst, sign):
+    h = C.c_void_p()
+    s, d, g = (np.ascontiguousarray(v, dt) for v, dt in
+               ((src, np.int32), (dst, np.int32), (sign, np.int8)))
+    code = rp.lib().rac_create_topology(n, s.size, s.ctypes.data, d.ctypes.data, g.ctypes.data,
+                                        C.byref(h))
+    return code, h
+
+
+@pytest.mark.parametrize("args", [
+    (0, [], [], []),                 # no genes
+    (2, [0], [2], [1]),              # index out of range
+    (2, [-1], [0], [1]),
+    (2, [0], [1], [0]),              # sign not +-1
+    (2, [0, 0], [1, 1], [1, -1]),    # duplicate edge
+])
+def test_topology_rejects_bad_input(args):
+    code, h = _topo(*args)
+    assert code == rp.EINVAL and not h.value
+    assert rp.last_error()
+
+
+def test_topology_too_large_is_unsupported():
+    code, _ = _topo(5000, [], [], [])
+    assert code == rp.EUNSUPPORTED
+
+
+def test_topology_canonical_order_and_self_loops():
+    t = rp.Topology(3, [2, 0, 1, 1], [0, 1, 1, 0], [1, -1, 1, -1])
+    assert list(zip(t.dst, t.src)) == sorted(zip([0, 1, 1, 0], [2, 0, 1, 1]))
+    assert t.n_edges == 4
+
+
+CASES = [
+    (inputs.toggle_switch(), 2001),
+    (inputs.toggle_switch_self_activation(), 7),
+    (inputs.erdos_renyi(10, 25, 1002), 2002),
+    (inputs.dense_core(1004), 2004),
+    (inputs.unregulated(3), 3),
+]
+
+
+@pytest.mark.parametrize("topo,seed", CASES, ids=[c[0].name for c in CASES])
+def test_sampler_matches_oracle_bit_exact(topo, seed):
+    t = rp.Topology.from_inputs(topo)
+    net = oracle.canonicalize(topo.n_genes, topo.src, topo.dst, topo.sign)
+    assert np.array_equal(t.src, net.src) and np.array_equal(t.dst, net.dst)
+    for begin, P, n_ic in [(0, 257, 7), (12345, 31, 1)]:
+        a = rp.sample_params(t, seed, P, n_ic, set_begin=begin)
+        b = oracle.sample(net, seed, P, n_ic, set_begin=begin)
+        for f in ("G", "k", "T", "lam", "n", "ic"):
+            assert np.array_equal(getattr(a, f), getattr(b, f)), f
+
+
+def test_sampler_custom_ranges_match_oracle():
+    topo = inputs.erdos_renyi(6, 10, 3)
+    t = rp.Topology.from_inputs(topo)
+    net = oracle.canonicalize(topo.n_genes, topo.src, topo.dst, topo.sign)
+    kw = dict(g_min=1, g_max=10, k_min=0.01, k_max=1, lam_act_min=2, lam_act_max=5,
+              lam_inh_min=0.1, lam_inh_max=0.5, n_min=2, n_max=3, t_lo=0.5, t_hi=1.5)
+    a = rp.sample_params(t, 9, 100, 3, ranges=rp.Ranges(**kw))
+    b = oracle.sample(net, 9, 100, 3, ranges=oracle.Ranges(**kw))
+    for f in ("G", "k", "T", "lam", "n", "ic"):
+        assert np.array_equal(getattr(a, f), getattr(b, f)), f
+
+
+def test_sampler_rejects_bad_ranges():
+    t = rp.Topology.from_inputs(inputs.toggle_switch())
+    with pytest.raises(rp.RacError) as e:
+        rp.sample_params(t, 1, 10, 1, ranges=rp.Ranges(k_min=0.0))
+    assert e.value.code == rp.EINVAL
+    with pytest.raises(rp.RacError):
+        rp.sample_params(t, 1, 10, 1, ranges=rp.Ranges(g_min=5, g_max=1))
+
+
+class _FakeTensor:
+    """Stands in for a device tensor: a non-NULL address that is never touched
+    because the call fails its argument checks first."""
+
+    def __init__(self, shape):
+        self.shape = shape
+
+    def data_ptr(self):
+        return 0x1000
+
+    @property
+    def device(self):
+        return "cuda"
+
+
+def _fake_params(N, E, P, n_ic):
+    return rp.DeviceParams(_FakeTensor((N, P)), _FakeTensor((N, P)), _FakeTensor((E, P)),
+                           _FakeTensor((E, P)), _FakeTensor((E, P)), _FakeTensor((n_ic, N)))
+
+
+def _fake_result():
+    return rp.Result(*[_FakeTensor((1,)) for _ in range(5)])
+
+
+@pytest.mark.parametrize("bad", [
+    dict(t_end=0.0), dict(rtol=0.0, atol=0.0), dict(rtol=-1.0), dict(max_steps=0),
+    dict(precision=7), dict(lanes_per_traj=3), dict(ss_atol=-1.0), dict(t0=float("nan")),
+])
+def test_steady_states_rejects_bad_options_before_enqueue(bad):
+    t = rp.Topology.from_inputs(inputs.toggle_switch())
+    with pytest.raises(rp.RacError) as e:
+        rp.steady_states(t, _fake_params(2, 2, 4, 2), rp.Opts(**bad), out=_fake_result(),
+                         stream=type("S", (), {"cuda_stream": 0})())
+    assert e.value.code == rp.EINVAL
+
+
+def test_integrate_rejects_unordered_times():
+    t = rp.Topology.from_inputs(inputs.toggle_switch())
+    s = type("S", (), {"cuda_stream": 0})()
+    for times in ([0.0, 2.0, 1.0], [-1.0, 1.0], [], [1.0, 1.0]):
+        with pytest.raises(rp.RacError) as e:
+            rp.integrate(t, _fake_params(2, 2, 4, 2), times, out=_fake_result(), stream=s)
+        assert e.value.code == rp.EINVAL
+
+
+def test_lane_choices():
+    ts = rp.Topology.from_inputs(inputs.toggle_switch())
+    assert ts.auto_lanes() >= 1 and ts.lanes_supported(1)
+    big = rp.Topology.from_inputs(inputs.erdos_renyi(100, 250, 5))
+    assert big.auto_lanes() >= 8
+    assert not big.lanes_supported(1)
+    assert not ts.lanes_supported(3)
