@@ -50,6 +50,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle trajectories (0 = auto)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy, whose FETCH_SIZE/WRITE_SIZE "
+                         "counters scale the kernel's HBM traffic figures")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -62,6 +65,12 @@ def main():
     from paper_2503_18356_amd import racipe as rp
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     topo = inputs.erdos_renyi(10, 25, seed=1002, inhib_frac=0.5)
     T = rp.Topology.from_inputs(topo)
     t0 = time.time()

@@ -86,43 +86,61 @@ __device__ __forceinline__ void wave_sync() {
 
 enum : int { kRunning = -1 };
 
+// LDS use per wave, in elements of R:
+//   [0, 64*GPL)                 source levels, index gene * n_groups + group
+//   [64*GPL, 64*(GPL+EPL+1))    running products, index slot * 64 + lane
+//   [64*(GPL+EPL+1), +64)       one write-only sink per lane (padding slots)
+// Every address a lane uses is precomputed as an absolute LDS byte offset.
+template <typename R, int EPL, int GPL>
+struct LdsLayout {
+    static constexpr int kSlots = GPL + EPL + 2;
+    static constexpr int kWaveElems = 64 * kSlots;
+};
+
 template <typename R, int EPL, int GPL, bool TS>
 __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
     using O = Ops<R>;
     using NT = typename O::NType;
-    constexpr int kSlots = GPL + EPL + 1;
-    __shared__ R lds[kBlock / 64][64 * kSlots];
+    using Lay = LdsLayout<R, EPL, GPL>;
+    static_assert(EPL % 4 == 0, "edge slots come in chunks of four");
+    __shared__ R lds[(kBlock / 64) * Lay::kWaveElems];
+    char* const lb = reinterpret_cast<char*>(lds);
+    auto ld = [&](uint32_t addr) -> R { return *reinterpret_cast<const R*>(lb + addr); };
+    auto st = [&](uint32_t addr, R v) { *reinterpret_cast<R*>(lb + addr) = v; };
+    constexpr uint32_t SZ = sizeof(R);
 
     const int lane = threadIdx.x & 63;
-    R* const lx = lds[threadIdx.x >> 6];  // [gene][group] source levels
-    R* const lp = lx + 64 * GPL;          // [slot][lane] running products
+    const uint32_t wave_elem = (threadIdx.x >> 6) * Lay::kWaveElems;
+    const uint32_t pre_base = (wave_elem + 64 * GPL + lane) * SZ;        // prefix[0] of this lane
+    const uint32_t sink = (wave_elem + 64 * (GPL + EPL + 1) + lane) * SZ;
 
     const int lpt = a.lpt;
     const int sh = __builtin_ctz(lpt);
     const int n_groups = 64 >> sh;
-    const int g = lane >> sh;   // group within the wave
-    const int r = lane & (lpt - 1);  // lane within the group
-    const uint64_t gmask = lpt == 64 ? ~0ull : (((1ull << lpt) - 1) << (g * lpt));
-    const int epl_rt = a.epl, gpl_rt = a.gpl;
+    const int g = lane >> sh;         // group within the wave
+    const int r = lane & (lpt - 1);   // lane within the group
+    const int gshift = g * lpt;
+    const uint64_t glow = lpt == 64 ? ~0ull : ((1ull << lpt) - 1);
     const Controls& c = a.c;
 
-    lp[lane] = (R)1;  // prefix[0] = 1
+    st(pre_base, (R)1);  // prefix[0] = 1, never overwritten
 
-    // Per-lane edge slots.
-    int e_src[EPL];
+    // Edge slots: source address, 1/T, n, sqrt(lam), 1/sqrt(lam) - sqrt(lam).
+    uint32_t e_xa[EPL];
     R e_invT[EPL], e_b[EPL], e_d[EPL];
     NT e_n[EPL];
-    // Per-lane gene slots.
+    // Gene slots: state, stages, G', k and LDS addresses (publish, prefix end/begin).
     R x[GPL], y[GPL], kk[7][GPL], gG[GPL], gk[GPL];
-    int g_pb[GPL], g_pe[GPL], g_xi[GPL], g_id[GPL];
+    uint32_t g_wa[GPL], g_pe[GPL], g_pb[GPL];
+    int g_id[GPL];
 #pragma unroll
     for (int s = 0; s < EPL; ++s) {
-        e_src[s] = g; e_invT[s] = 0; e_b[s] = 1; e_d[s] = 0; e_n[s] = O::to_n(1);
+        e_xa[s] = sink; e_invT[s] = 0; e_b[s] = 1; e_d[s] = 0; e_n[s] = O::to_n(1);
     }
 #pragma unroll
     for (int q = 0; q < GPL; ++q) {
         x[q] = 0; y[q] = 0; gG[q] = 0; gk[q] = 0;
-        g_pb[q] = lane; g_pe[q] = lane; g_xi[q] = 0; g_id[q] = -1;
+        g_wa[q] = sink; g_pe[q] = pre_base; g_pb[q] = pre_base; g_id[q] = -1;
 #pragma unroll
         for (int l = 0; l < 7; ++l) kk[l][q] = 0;
     }
@@ -136,57 +154,68 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
     uint64_t popped = 0;  // queue position after this wave's last pop
     int n_genes = 1;
 
-    // Network descriptor by value: from the device table or the kernel argument.
-    auto desc = [&](int id) -> NetDesc { return a.nets ? a.nets[id] : a.net0; };
-
-    // One right-hand-side evaluation f(yv) for every lane of the wave.
+    // One right-hand-side evaluation f(yv) for every lane of the wave: no
+    // branches, padding slots evaluate factors of exactly 1.
     auto rhs = [&](const R (&yv)[GPL], R (&f)[GPL]) {
 #pragma unroll
-        for (int q = 0; q < GPL; ++q)
-            if (q < gpl_rt && g_id[q] >= 0) lx[g_xi[q]] = yv[q] > (R)0 ? yv[q] : (R)0;
+        for (int q = 0; q < GPL; ++q) st(g_wa[q], yv[q] > (R)0 ? yv[q] : (R)0);
         wave_sync();
         R run = 1;
 #pragma unroll
-        for (int s = 0; s < EPL; ++s) {
-            if (s < epl_rt) {
-                run *= O::hill(lx[e_src[s]], e_invT[s], e_n[s], e_b[s], e_d[s]);
-                lp[(s + 1) * 64 + lane] = run;
+        for (int c0 = 0; c0 < EPL; c0 += 4) {
+            R hv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                hv[j] = O::hill(ld(e_xa[c0 + j]), e_invT[c0 + j], e_n[c0 + j], e_b[c0 + j], e_d[c0 + j]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                run *= hv[j];
+                st(pre_base + (uint32_t)(c0 + j + 1) * 64 * SZ, run);
             }
         }
         wave_sync();
 #pragma unroll
-        for (int q = 0; q < GPL; ++q)
-            f[q] = q < gpl_rt ? gG[q] * (lp[g_pe[q]] * O::rcp(lp[g_pb[q]])) - gk[q] * yv[q] : (R)0;
+        for (int q = 0; q < GPL; ++q) f[q] = gG[q] * (ld(g_pe[q]) * O::rcp(ld(g_pb[q]))) - gk[q] * yv[q];
     };
 
     auto group_sum = [&](double v) {
         for (int m = 1; m < lpt; m <<= 1) v += __shfl_xor(v, m);
         return v;
     };
-    auto group_all = [&](bool p) { return (__ballot(p) & gmask) == gmask; };
+    auto group_sumf = [&](float v) {
+        for (int m = 1; m < lpt; m <<= 1) v += __shfl_xor(v, m);
+        return v;
+    };
+    auto group_all = [&](bool p) { return ((__ballot(p) >> gshift) & glow) == glow; };
 
     // Write the end-of-trajectory record and free the group.
     auto finish = [&](int status) {
-        const NetDesc d = desc(net);
+        const NetDesc* dp = a.nets ? a.nets + net : nullptr;
+#define RAC_DF(field) (dp ? dp->field : a.net0.field)
+        const int N = RAC_DF(n_genes);
+        R* const xo = (R*)RAC_DF(x_out) + local * (int64_t)(TS ? a.n_t : 1) * N;
         if (!TS) {
-            R* xo = (R*)d.x_out + local * d.n_genes;
 #pragma unroll
             for (int q = 0; q < GPL; ++q)
-                if (q < gpl_rt && g_id[q] >= 0) xo[g_id[q]] = x[q];
+                if (g_id[q] >= 0) xo[g_id[q]] = x[q];
         } else {
             // Steady before the last output: the remaining outputs hold x_ss.
-            R* xo = (R*)d.x_out + local * (int64_t)a.n_t * d.n_genes;
             for (int k = kout; k < a.n_t; ++k)
 #pragma unroll
                 for (int q = 0; q < GPL; ++q)
-                    if (q < gpl_rt && g_id[q] >= 0) xo[(int64_t)k * d.n_genes + g_id[q]] = x[q];
+                    if (g_id[q] >= 0) xo[(int64_t)k * N + g_id[q]] = x[q];
         }
         if (r == 0) {
-            if (d.t_final) d.t_final[local] = t;
-            if (d.status) d.status[local] = (int8_t)status;
-            if (d.n_acc) d.n_acc[local] = nacc;
-            if (d.n_rej) d.n_rej[local] = nrej;
+            double* tf = RAC_DF(t_final);
+            int8_t* sp = RAC_DF(status);
+            int32_t* na = RAC_DF(n_acc);
+            int32_t* nr = RAC_DF(n_rej);
+            if (tf) tf[local] = t;
+            if (sp) sp[local] = (int8_t)status;
+            if (na) na[local] = nacc;
+            if (nr) nr[local] = nrej;
         }
+#undef RAC_DF
         traj = -1;
         fresh = false;
     };
@@ -207,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
                 popped = base + (unsigned long long)nfree;
                 if (base + (unsigned long long)nfree >= (unsigned long long)a.total) exhausted = true;
                 if (traj < 0) {
-                    const int rank = __popcll(free_lead & ((1ull << (g * lpt)) - 1ull));
+                    const int rank = __popcll(free_lead & ((1ull << gshift) - 1ull));
                     const int64_t idx = (int64_t)base + rank;
                     if (idx < a.total) {
                         // Which network: binary search over first queue indices.
@@ -224,7 +253,8 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
                         // the scheduler from hoisting them all), which keeps
                         // this rarely taken path from setting the kernel's
                         // register peak next to the live trajectory state.
-#define RAC_DF(field) (a.nets ? a.nets[net].field : a.net0.field)
+                        const NetDesc* dp = a.nets ? a.nets + net : nullptr;
+#define RAC_DF(field) (dp ? dp->field : a.net0.field)
                         traj = idx;
                         local = idx - RAC_DF(traj_begin);
                         const int n_ic = RAC_DF(n_ic);
@@ -242,18 +272,18 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
 #pragma unroll
                         for (int s = 0; s < EPL; ++s) {
                             asm volatile("" ::: "memory");
-                            const int pk = (s < epl_rt && s < stride) ? lane_edge[s] : -1;
+                            const int pk = s < stride ? lane_edge[s] : -1;
                             if (pk >= 0) {
                                 const int e = pk & 0xffff, src = pk >> 16;
                                 const R Tv = (R)Tp[e * P];
                                 const R sl = O::sqrt((R)Lp[e * P]);
-                                e_src[s] = src * n_groups + g;
+                                e_xa[s] = (wave_elem + (uint32_t)(src * n_groups + g)) * SZ;
                                 e_invT[s] = (R)1 / Tv;
                                 e_n[s] = O::to_n((int)Np[e * P]);
                                 e_b[s] = sl;
                                 e_d[s] = (R)1 / sl - sl;
                             } else {
-                                e_src[s] = g; e_invT[s] = 0; e_b[s] = 1; e_d[s] = 0; e_n[s] = O::to_n(1);
+                                e_xa[s] = sink; e_invT[s] = 0; e_b[s] = 1; e_d[s] = 0; e_n[s] = O::to_n(1);
                             }
                         }
                         const float* Gp = RAC_DF(G) + p;
@@ -262,11 +292,12 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
                         const int32_t* row_ptr = RAC_DF(row_ptr);
                         const int32_t* gene_row = RAC_DF(gene_row);
                         const int8_t* sign = RAC_DF(sign);
+#undef RAC_DF
 #pragma unroll
                         for (int q = 0; q < GPL; ++q) {
                             asm volatile("" ::: "memory");
                             const int gene = r + q * lpt;
-                            if (q < gpl_rt && gene < n_genes) {
+                            if (gene < n_genes) {
                                 const R Gv = (R)Gp[gene * P];
                                 const R kv = (R)Kp[gene * P];
                                 // Fold each row's sqrt(lam) (and, for activation
@@ -278,21 +309,20 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
                                 }
                                 const int row = gene_row[gene];
                                 const int rl = row & 0xff, pb = (row >> 8) & 0xff, pe = (row >> 16) & 0xff;
-                                const int rowlane = g * lpt + rl;
+                                const uint32_t rowlane = (uint32_t)(gshift + rl);
                                 g_id[q] = gene;
-                                g_xi[q] = gene * n_groups + g;
-                                g_pb[q] = pb * 64 + rowlane;
-                                g_pe[q] = pe * 64 + rowlane;
+                                g_wa[q] = (wave_elem + (uint32_t)(gene * n_groups + g)) * SZ;
+                                g_pb[q] = (wave_elem + 64 * GPL + (uint32_t)pb * 64 + rowlane) * SZ;
+                                g_pe[q] = (wave_elem + 64 * GPL + (uint32_t)pe * 64 + rowlane) * SZ;
                                 gG[q] = gf;
                                 gk[q] = kv;
                                 const R u = (R)icp[gene];
                                 x[q] = c.ic_absolute ? u : u * Gv / kv;
                             } else {
-                                g_id[q] = -1; g_xi[q] = 0; g_pb[q] = lane; g_pe[q] = lane;
+                                g_id[q] = -1; g_wa[q] = sink; g_pb[q] = pre_base; g_pe[q] = pre_base;
                                 gG[q] = 0; gk[q] = 0; x[q] = 0;
                             }
                         }
-#undef RAC_DF
                         t = c.t0;
                         t_stop = TS ? a.t_out[a.n_t - 1] : c.t_end;
                         nacc = 0; nrej = 0; kout = 0; last_rej = false;
@@ -307,56 +337,56 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
         }
 
         // ---- start new trajectories: f(x0), steady test at t0, first step -
+        // (Hairer, Norsett, Wanner I, Sec. II.4 starting step; its norms are a
+        // heuristic, evaluated in FP32.)
         if (__ballot(fresh) != 0) {
 #pragma unroll
             for (int q = 0; q < GPL; ++q) y[q] = x[q];
             rhs(y, kk[1]);
-            bool fin = true;
-            double s0 = 0, s1 = 0;
+            bool fin = true, steady = true;
+            float s0 = 0, s1 = 0;
 #pragma unroll
             for (int q = 0; q < GPL; ++q) {
                 if (fresh) kk[0][q] = kk[1][q];
-                if (q < gpl_rt && g_id[q] >= 0) {
-                    fin = fin && __builtin_isfinite((double)x[q]) && __builtin_isfinite((double)kk[1][q]);
-                    const double isc = 1.0 / (c.atol + c.rtol * fabs((double)x[q]));
-                    s0 += ((double)x[q] * isc) * ((double)x[q] * isc);
-                    s1 += ((double)kk[1][q] * isc) * ((double)kk[1][q] * isc);
+                if (g_id[q] >= 0) {
+                    const float xv = (float)x[q], fv = (float)kk[1][q];
+                    fin = fin && __builtin_isfinite(xv) && __builtin_isfinite(fv);
+                    const float isc = 1.0f / ((float)c.atol + (float)c.rtol * fabsf(xv));
+                    s0 += (xv * isc) * (xv * isc);
+                    s1 += (fv * isc) * (fv * isc);
+                    steady = steady && fabs((double)kk[1][q]) <=
+                                           c.ss_atol + c.ss_rtol * (double)gk[q] * fabs((double)x[q]);
                 }
             }
             const bool all_fin = group_all(fin);
-            bool steady = true;
-#pragma unroll
-            for (int q = 0; q < GPL; ++q)
-                if (q < gpl_rt && g_id[q] >= 0)
-                    steady = steady && fabs((double)kk[1][q]) <=
-                                           c.ss_atol + c.ss_rtol * (double)gk[q] * fabs((double)x[q]);
             const bool all_steady = group_all(steady);
-            const double d0 = sqrt(group_sum(s0) / n_genes), d1 = sqrt(group_sum(s1) / n_genes);
+            const float d0 = sqrtf(group_sumf(s0) / n_genes), d1 = sqrtf(group_sumf(s1) / n_genes);
             if (TS && fresh) {
-                const NetDesc d = desc(net);
-                R* xo = (R*)d.x_out + local * (int64_t)a.n_t * d.n_genes;
+                const NetDesc* dp = a.nets ? a.nets + net : nullptr;
+                const int N = dp ? dp->n_genes : a.net0.n_genes;
+                R* xo = (R*)(dp ? dp->x_out : a.net0.x_out) + local * (int64_t)a.n_t * N;
                 while (kout < a.n_t && a.t_out[kout] <= t) {
 #pragma unroll
                     for (int q = 0; q < GPL; ++q)
-                        if (q < gpl_rt && g_id[q] >= 0) xo[(int64_t)kout * d.n_genes + g_id[q]] = x[q];
+                        if (g_id[q] >= 0) xo[(int64_t)kout * N + g_id[q]] = x[q];
                     ++kout;
                 }
             }
-            const double hmax = t_stop - c.t0;
-            double hg = (d0 < 1e-10 || d1 < 1e-10) ? 1e-6 : 0.01 * d0 / d1;
+            const float hmax = (float)(t_stop - c.t0);
+            float hg = (d0 < 1e-10f || d1 < 1e-10f) ? 1e-6f : 0.01f * d0 / d1;
             hg = hg < hmax ? hg : hmax;
 #pragma unroll
             for (int q = 0; q < GPL; ++q) y[q] = x[q] + (R)hg * kk[0][q];
             rhs(y, kk[2]);
-            double s2 = 0;
+            float s2 = 0;
 #pragma unroll
             for (int q = 0; q < GPL; ++q)
-                if (q < gpl_rt && g_id[q] >= 0) {
-                    const double dv = ((double)kk[2][q] - (double)kk[0][q]) /
-                                      (c.atol + c.rtol * fabs((double)x[q]));
+                if (g_id[q] >= 0) {
+                    const float dv = (float)(kk[2][q] - kk[0][q]) /
+                                     ((float)c.atol + (float)c.rtol * fabsf((float)x[q]));
                     s2 += dv * dv;
                 }
-            const double d2 = sqrt(group_sum(s2) / n_genes) / hg;
+            const float d2 = sqrtf(group_sumf(s2) / n_genes) / hg;
             if (fresh) {
                 if (!all_fin) {
                     finish(RAC_NONFINITE);
@@ -364,15 +394,17 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
                     finish(RAC_CONVERGED);
                 } else if (t >= t_stop) {
                     finish(RAC_T_END);
-                } else if (c.h0 > 0) {
-                    h = c.h0 < hmax ? c.h0 : hmax;
-                    fresh = false;
                 } else {
-                    const double der = d1 > d2 ? d1 : d2;
-                    const double h1 = der <= 1e-15 ? (1e-6 > hg * 1e-3 ? 1e-6 : hg * 1e-3)
-                                                   : ::pow(0.01 / der, 0.2);
-                    double hh = 100.0 * hg < h1 ? 100.0 * hg : h1;
-                    h = hh <= hmax ? hh : hmax;
+                    const double hm = t_stop - c.t0;
+                    if (c.h0 > 0) {
+                        h = c.h0 < hm ? c.h0 : hm;
+                    } else {
+                        const float der = d1 > d2 ? d1 : d2;
+                        const float h1 = der <= 1e-15f ? fmaxf(1e-6f, hg * 1e-3f)
+                                                       : __builtin_amdgcn_exp2f(0.2f * __builtin_amdgcn_logf(0.01f / der));
+                        const double hh = (double)fminf(100.0f * hg, h1);
+                        h = hh <= hm ? hh : hm;
+                    }
                     fresh = false;
                 }
             }
@@ -399,34 +431,32 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
         }
         const R hR = (R)hs;
 #pragma unroll
-        for (int st = 1; st < 7; ++st) {
+        for (int st_ = 1; st_ < 7; ++st_) {
 #pragma unroll
             for (int q = 0; q < GPL; ++q) {
-                R acc = (R)kA[st][0] * kk[0][q];
+                R acc = (R)kA[st_][0] * kk[0][q];
 #pragma unroll
-                for (int l = 1; l < st; ++l)
-                    if (kA[st][l] != 0.0) acc += (R)kA[st][l] * kk[l][q];
+                for (int l = 1; l < st_; ++l)
+                    if (kA[st_][l] != 0.0) acc += (R)kA[st_][l] * kk[l][q];
                 y[q] = x[q] + hR * acc;
             }
-            rhs(y, kk[st]);
+            rhs(y, kk[st_]);
         }
         // y now holds the fifth-order solution, kk[6] its derivative.
         double serr = 0;
         bool fin = true;
 #pragma unroll
         for (int q = 0; q < GPL; ++q) {
-            if (q < gpl_rt && g_id[q] >= 0) {
-                R e = (R)kErr[0] * kk[0][q];
+            R e = (R)kErr[0] * kk[0][q];
 #pragma unroll
-                for (int l = 2; l < 7; ++l) e += (R)kErr[l] * kk[l][q];
-                // Scaled error e_i / (atol + rtol max(|x_i|, |x_new,i|)); the
-                // ratio in R, its square accumulated in FP64.
-                const R ax = x[q] < 0 ? -x[q] : x[q], an = y[q] < 0 ? -y[q] : y[q];
-                const R sc = (R)c.atol + (R)c.rtol * (ax > an ? ax : an);
-                const double rq = (double)(hR * e * O::rcp(sc));
-                serr += rq * rq;
-                fin = fin && __builtin_isfinite((double)y[q]);
-            }
+            for (int l = 2; l < 7; ++l) e += (R)kErr[l] * kk[l][q];
+            // Scaled error e_i / (atol + rtol max(|x_i|, |x_new,i|)); the ratio
+            // in R, its square accumulated in FP64.
+            const R ax = x[q] < 0 ? -x[q] : x[q], an = y[q] < 0 ? -y[q] : y[q];
+            const R sc = (R)c.atol + (R)c.rtol * (ax > an ? ax : an);
+            const double rq = g_id[q] >= 0 ? (double)(hR * e * O::rcp(sc)) : 0.0;
+            serr += rq * rq;
+            fin = fin && (g_id[q] < 0 || __builtin_isfinite((double)y[q]));
         }
         const double err = sqrt(group_sum(serr) / n_genes);
         const bool all_fin = group_all(fin);  // collective: evaluated by every lane
@@ -440,15 +470,16 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
         }
         // Dense output for every output time inside the accepted step.
         if (TS && accept && kout < a.n_t && a.t_out[kout] <= (clipped ? t_stop : t + hs)) {
-            const NetDesc d = desc(net);
-            R* xo = (R*)d.x_out + local * (int64_t)a.n_t * d.n_genes;
+            const NetDesc* dp = a.nets ? a.nets + net : nullptr;
+            const int N = dp ? dp->n_genes : a.net0.n_genes;
+            R* xo = (R*)(dp ? dp->x_out : a.net0.x_out) + local * (int64_t)a.n_t * N;
             const double t_new = clipped ? t_stop : t + hs;
             while (kout < a.n_t && a.t_out[kout] <= t_new) {
                 const R th = (R)((a.t_out[kout] - t) / hs);
                 const R th1 = (R)1 - th;
 #pragma unroll
                 for (int q = 0; q < GPL; ++q) {
-                    if (q < gpl_rt && g_id[q] >= 0) {
+                    if (g_id[q] >= 0) {
                         const R ydiff = y[q] - x[q];
                         const R bspl = hR * kk[0][q] - ydiff;
                         const R c4 = ydiff - hR * kk[6][q] - bspl;
@@ -456,8 +487,8 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
 #pragma unroll
                         for (int l = 2; l < 7; ++l) c5 += (R)kDense[l] * kk[l][q];
                         c5 *= hR;
-                        const R v = x[q] + th * (ydiff + th1 * (bspl + th * (c4 + th1 * c5)));
-                        xo[(int64_t)kout * d.n_genes + g_id[q]] = v;
+                        xo[(int64_t)kout * N + g_id[q]] =
+                            x[q] + th * (ydiff + th1 * (bspl + th * (c4 + th1 * c5)));
                     }
                 }
                 ++kout;
@@ -471,9 +502,9 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
             for (int q = 0; q < GPL; ++q) {
                 x[q] = y[q];
                 kk[0][q] = kk[6][q];
-                if (q < gpl_rt && g_id[q] >= 0)
-                    steady = steady && fabs((double)kk[0][q]) <=
-                                           c.ss_atol + c.ss_rtol * (double)gk[q] * fabs((double)x[q]);
+                steady = steady && (g_id[q] < 0 ||
+                                    fabs((double)kk[0][q]) <=
+                                        c.ss_atol + c.ss_rtol * (double)gk[q] * fabs((double)x[q]));
             }
             double fac = err > 0 ? 0.9 * O::pow_m15(err) : 10.0;
             const double fmax = last_rej ? 1.0 : 10.0;

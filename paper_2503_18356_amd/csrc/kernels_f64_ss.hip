@@ -8,8 +8,9 @@ namespace rac {
 #define RAC_K(E, G) {RAC_FP64, false, E, G, reinterpret_cast<const void*>(&dp5_kernel<double, E, G, false>)}
 
 static const KernelEntry kTable[] = {
-    RAC_K(4, 1), RAC_K(4, 2), RAC_K(4, 4),  RAC_K(8, 1), RAC_K(8, 2),
-    RAC_K(8, 4), RAC_K(16, 1), RAC_K(16, 2), RAC_K(32, 1),
+    RAC_K(4, 1), RAC_K(4, 2), RAC_K(4, 3), RAC_K(4, 4), RAC_K(4, 6), RAC_K(8, 1), RAC_K(8, 2),
+    RAC_K(8, 3), RAC_K(8, 4), RAC_K(12, 1), RAC_K(12, 2), RAC_K(12, 3), RAC_K(16, 1),
+    RAC_K(16, 2),
 };
 
 int kernels_f64_ss(const KernelEntry** out) {

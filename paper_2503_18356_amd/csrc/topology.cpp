@@ -28,7 +28,7 @@ Shape pick_shape(int epl, int gpl, int precision) {
     Shape best{0, 0};
     auto consider = [&](const Shape& s) {
         if (s.epl < epl || s.gpl < gpl) return;
-        if (best.epl == 0 || 5 * s.epl + 15 * s.gpl < 5 * best.epl + 15 * best.gpl) best = s;
+        if (best.epl == 0 || 14 * s.epl + 25 * s.gpl < 14 * best.epl + 25 * best.gpl) best = s;
     };
     if (precision == RAC_FP64)
         for (const Shape& s : kShapesF64) consider(s);
@@ -103,7 +103,9 @@ int auto_lanes(const rac_topology* t, int precision) {
     for (int lpt = 1; lpt <= kWave; lpt *= 2) {
         if (!plan_fits(t, lpt, precision)) continue;
         const LanePlan* p = get_plan(t, lpt);
-        double cost = lpt * (14.0 * p->epl + 30.0 * p->gpl + 40.0);
+        // Padded slots are evaluated too, so cost the compiled shape.
+        const Shape s = pick_shape(std::max(p->epl, 1), p->gpl, precision);
+        double cost = lpt * (14.0 * s.epl + 25.0 * s.gpl + 40.0);
         if (best == 0 || cost < best_cost) {
             best = lpt;
             best_cost = cost;

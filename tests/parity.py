@@ -70,11 +70,25 @@ class Report:
                 f"(excused {self.excused_flips}) slow={self.slow} unexcused={len(self.unexcused)}")
 
 
+def bound_of(net, prm, traj, n_ic, divide=True):
+    """Per-component upper bound of x: G/k when activating terms are divided
+    by lambda (Eq. 1 as printed), G * prod_act lambda / k otherwise."""
+    gk = gk_of(prm, traj, n_ic)
+    if divide:
+        return gk
+    p = np.asarray(traj) // n_ic
+    fac = np.ones_like(gk)
+    for e in range(net.n_edges):
+        if net.sign[e] > 0:
+            fac[:, net.dst[e]] *= np.maximum(1.0, prm.lam[e, p].astype(np.float64))
+    return gk * fac
+
+
 def compare_steady(net, prm, opts, traj, x_gpu, x_ref, n_ic, adjudicate=True) -> Report:
     """x_gpu, x_ref: [n][N] for trajectories `traj` (ids p * n_ic + c)."""
     x_gpu = np.asarray(x_gpu, np.float64)
     x_ref = np.asarray(x_ref, np.float64)
-    gk = gk_of(prm, traj, n_ic)
+    gk = bound_of(net, prm, traj, n_ic, bool(opts.divide_act_by_lambda))
     err = np.abs(x_gpu - x_ref) / gk
     rel = np.abs(x_gpu - x_ref) / np.maximum(np.abs(x_ref), 1e-12)
     bad = np.flatnonzero(err.max(axis=1) > TOL)
