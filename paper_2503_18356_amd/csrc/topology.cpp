@@ -1,6 +1,7 @@
 // Topology handle, error reporting and the lane plans that spread one network
 // over the lanes of a trajectory group.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -94,9 +95,19 @@ bool plan_fits(const rac_topology* t, int lpt, int precision) {
     return pick_shape(std::max(p->epl, 1), p->gpl, precision).epl != 0;
 }
 
-// Heuristic lane count: the feasible lpt with the least estimated issue work
-// per trajectory step (lanes x (edge slots x edge cost + gene slots x gene
-// cost + control)), ties to the smaller lpt.
+// Heuristic lane count when the caller gives none: minimise estimated issue
+// work per trajectory step, lanes x (edge slots x 14 + gene slots x 25 + 40),
+// divided by a latency-hiding efficiency that falls with the shape's register
+// footprint (waves per SIMD).  The constants come from timing the kernel
+// shapes on MI355X; the autotuner measures instead of estimating.
+static double shape_efficiency(const Shape& s, int precision) {
+    const double vgpr = precision == RAC_FP64 ? 70.0 + 10.0 * s.epl + 32.0 * s.gpl
+                                              : 58.0 + 5.0 * s.epl + 17.0 * s.gpl;
+    const int waves = vgpr > 256 ? 1 : std::min(8, (int)(512.0 / (8.0 * std::ceil(vgpr / 8.0))));
+    static const double eff[] = {0.0, 0.30, 0.54, 0.71, 0.88, 1.0, 1.0, 1.0, 1.0};
+    return eff[waves];
+}
+
 int auto_lanes(const rac_topology* t, int precision) {
     int best = 0;
     double best_cost = 0;
@@ -105,7 +116,7 @@ int auto_lanes(const rac_topology* t, int precision) {
         const LanePlan* p = get_plan(t, lpt);
         // Padded slots are evaluated too, so cost the compiled shape.
         const Shape s = pick_shape(std::max(p->epl, 1), p->gpl, precision);
-        double cost = lpt * (14.0 * s.epl + 25.0 * s.gpl + 40.0);
+        const double cost = lpt * (14.0 * s.epl + 25.0 * s.gpl + 40.0) / shape_efficiency(s, precision);
         if (best == 0 || cost < best_cost) {
             best = lpt;
             best_cost = cost;
