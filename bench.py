@@ -30,12 +30,28 @@ PEAK_FP32 = 157.3e12   # MI355X FP32 vector, TFLOP/s (packed)
 PEAK_HBM = 8.0e12
 
 
-def credited_flops(topo, hp, n_ic, steps_per_traj):
-    """Algorithmic FP32 work: per attempted step 6 right-hand sides of
-    sum_e (6 + c(n_e)) + 3N flops plus 56N flops of stage/error arithmetic;
-    c(n) is the shortest multiplication chain for x^n."""
-    from paper_2503_18356_amd import flops
-    return flops.credited(topo.n_genes, hp.n, n_ic, steps_per_traj)
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("dp5_kernel.h", "kernel_common.h"):
+        with open(os.path.join(ROOT, "paper_2503_18356_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    import glob
+    import re
+    want = kernel_source_hash()
+    for f in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        txt = open(f).read()
+        m = re.search(r"`traffic_bytes_per_launch: (\d+)` `kernel_source_hash: ([0-9a-f]+)` "
+                      r"`workload: ([\w.]+)`", txt)
+        if m and m.group(2) == want and m.group(3) == workload:
+            return float(m.group(1))
+    return None
 
 
 def main():
@@ -135,7 +151,8 @@ def main():
             "peak": PEAK_FP32 / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32,
-            "traffic": None,
+            "traffic": measured_traffic("er10_1e6_fp32") if (args.n_sets, args.n_ic, args.lanes) == (10000, 100, 0) else None,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "hbm_frac": bytes_per_launch / (lat.mean() * 1e-3) / PEAK_HBM,
         },
