@@ -146,6 +146,14 @@ rac_status rac_sample_params(const rac_topology* topo, const rac_ranges* ranges,
                              int64_t set_begin, int64_t n_sets, int32_t n_ic,
                              rac_params_view* out, float* ic_frac);
 
+/* The same sampling on the GPU, bit-identical to rac_sample_params: dev_out
+ * and dev_ic_frac (may be NULL) are device arrays; the work is enqueued on
+ * hip_stream (asynchronous).  Argument errors as rac_sample_params. */
+rac_status rac_sample_params_device(const rac_topology* topo, const rac_ranges* ranges,
+                                    uint64_t seed, int64_t set_begin, int64_t n_sets,
+                                    int32_t n_ic, rac_params_view* dev_out, float* dev_ic_frac,
+                                    void* hip_stream);
+
 /* ------------------------------------------------------------------------ */
 /* Integration (Sec. 2.1.3).                                                  */
 /* ------------------------------------------------------------------------ */
@@ -223,10 +231,65 @@ typedef struct {
 rac_status rac_steady_states_batch(const rac_batch_item* items, int32_t n_items,
                                    const rac_solver_opts* opts, void* hip_stream);
 
+/* ------------------------------------------------------------------------ */
+/* Serving step batches (continuous batching of simulation requests).        */
+/* ------------------------------------------------------------------------ */
+/* A server owns a device work queue, a table of admitted requests and a slot
+ * table holding the state of in-flight trajectories between batches.  Each
+ * rac_server_step enqueues one step batch: a persistent launch of the
+ * bounded DP5 kernel (RAC_FP32, lanes_per_traj lanes per trajectory, kernel
+ * shape (epl, gpl)) that resumes the parked trajectories, pulls new ones
+ * from the queue as lanes free up, runs at most batch_steps loop iterations
+ * per wave and parks what is unfinished.  The launch has fixed arguments
+ * and is captured into a hipGraph on the first call and replayed after.
+ * Requests submitted while others are in flight join the queue and share
+ * the same launches; each trajectory's result is the same as from
+ * rac_steady_states with the same opts and lane count.
+ * Ownership: the server owns its device memory (request table of
+ * max_requests entries, slot table sized for one full grid); submitted
+ * arrays stay caller-owned and must stay valid until the request's done
+ * count reaches P * n_ic.  One server is used from one stream at a time. */
+typedef struct rac_server rac_server;
+
+/* EINVAL: bad opts, lanes_per_traj < 1, max_requests < 1, batch_steps < 1.
+ * EUNSUPPORTED: precision other than RAC_FP32, or no compiled (epl, gpl).
+ * ENOMEM: device allocation failed. */
+rac_status rac_server_create(const rac_solver_opts* opts, int32_t epl, int32_t gpl,
+                             int32_t max_requests, int32_t batch_steps, rac_server** out);
+void rac_server_destroy(rac_server* s);
+
+/* Admit a request (arguments as rac_steady_states); enqueues two small
+ * uploads on hip_stream and returns its id (0, 1, ...).  EUNSUPPORTED if the
+ * network's lane plan does not fit the server's shape; ENOMEM if the request
+ * table is full. */
+rac_status rac_server_submit(rac_server* s, const rac_topology* topo,
+                             const rac_params_view* dev_params, const float* dev_ic,
+                             int32_t n_ic, void* dev_x_out, const rac_traj_info* dev_info,
+                             void* hip_stream, int32_t* request_id);
+
+/* Enqueue one step batch on hip_stream (graph replay).  EINVAL for the null
+ * stream, which cannot be captured. */
+rac_status rac_server_step(rac_server* s, void* hip_stream);
+
+/* Enqueue a copy of the finished-trajectory counts of requests
+ * [first, first + count) into host_out (host); valid after the stream syncs. */
+rac_status rac_server_done_counts(rac_server* s, int32_t first, int32_t count, int32_t* host_out,
+                                  void* hip_stream);
+
+/* Submitted requests, queued trajectories in total, waves per step batch and
+ * slot-table bytes (any pointer may be NULL). */
+rac_status rac_server_info(const rac_server* s, int32_t* n_requests, int64_t* total_trajectories,
+                           int32_t* grid_waves, int64_t* slot_bytes);
+
 /* The lanes-per-trajectory choice the library would make for a network
  * (0 if none fits), and whether a given choice fits the compiled kernels. */
 int32_t rac_auto_lanes(const rac_topology* topo, int32_t precision);
 int32_t rac_lanes_supported(const rac_topology* topo, int32_t precision, int32_t lanes);
+
+/* The compiled kernel shape (edge slots, gene slots per lane) a network uses
+ * at a lane count.  EUNSUPPORTED if none fits. */
+rac_status rac_plan_shape(const rac_topology* topo, int32_t precision, int32_t lanes, int32_t* epl,
+                          int32_t* gpl);
 
 #ifdef __cplusplus
 }

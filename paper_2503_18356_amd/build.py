@@ -14,8 +14,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librac.so")
 
 HOST_SRC = ["topology.cpp", "sampler.cpp"]
-HIP_SRC = ["solver.hip", "kernels_f32_ss.hip", "kernels_f32_ts.hip", "kernels_f64_ss.hip",
-           "kernels_f64_ts.hip"]
+HIP_SRC = ["solver.hip", "sampler_device.hip", "kernels_f32_ss.hip", "kernels_f32_ts.hip", "kernels_f64_ss.hip",
+           "kernels_f64_ts.hip", "kernels_f32_serve.hip", "server.hip"]
 # Packed FP32 instructions are kept out of every HIP object.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=fast",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

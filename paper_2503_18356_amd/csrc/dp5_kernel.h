@@ -97,8 +97,9 @@ struct LdsLayout {
     static constexpr int kWaveElems = 64 * kSlots;
 };
 
-template <typename R, int EPL, int GPL, bool TS>
+template <typename R, int EPL, int GPL, bool TS, bool BOUNDED = false>
 __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
+    static_assert(!(TS && BOUNDED), "serving step batches run in steady-state mode");
     using O = Ops<R>;
     using NT = typename O::NType;
     using Lay = LdsLayout<R, EPL, GPL>;
@@ -214,125 +215,216 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
             if (sp) sp[local] = (int8_t)status;
             if (na) na[local] = nacc;
             if (nr) nr[local] = nrej;
+            int32_t* dn = RAC_DF(done);
+            if (dn) atomicAdd(dn, 1);
         }
 #undef RAC_DF
         traj = -1;
         fresh = false;
     };
 
-    for (;;) {
+    // Saved state of a wave between serving step batches, lane fastest:
+    // x[GPL], k1[GPL] (R); t, h (f64); trajectory id (i64); accepted,
+    // rejected, flags (i32; bit 0 last step rejected, bit 1 not yet started).
+    constexpr size_t kOffK = (size_t)64 * GPL * SZ, kOffT = 2 * kOffK, kOffH = kOffT + 512,
+                     kOffTraj = kOffH + 512, kOffAcc = kOffTraj + 512, kOffRej = kOffAcc + 256,
+                     kOffFlags = kOffRej + 256, kSlotBytes = kOffFlags + 256;
+    static_assert(kSlotBytes == serve_slot_bytes(GPL, SZ), "slot layout");
+    char* const sbase =
+        BOUNDED ? a.slots + (size_t)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * kSlotBytes : nullptr;
+
+    // Start trajectory idx (a global queue index) in this lane's group: find
+    // its network, load and derive its parameters, set x0.
+    auto load_traj = [&](int64_t idx) {
+            // Which network: binary search over first queue indices.
+            net = 0;
+            if (a.nets) {
+                int lo = 0, hi = (BOUNDED ? __hip_atomic_load(&a.ctl->n_nets, __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_AGENT)
+                                          : a.n_nets) - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (a.nets[mid].traj_begin <= idx) lo = mid; else hi = mid - 1;
+                }
+                net = lo;
+            }
+            // Loads go one slot at a time (the memory clobbers stop
+            // the scheduler from hoisting them all), which keeps
+            // this rarely taken path from setting the kernel's
+            // register peak next to the live trajectory state.
+            const NetDesc* dp = a.nets ? a.nets + net : nullptr;
+#define RAC_DF(field) (dp ? dp->field : a.net0.field)
+            traj = idx;
+            local = idx - RAC_DF(traj_begin);
+            const int n_ic = RAC_DF(n_ic);
+            int64_t p = (int64_t)((double)local * RAC_DF(inv_n_ic));
+            if (p * n_ic > local) --p;
+            if ((p + 1) * n_ic <= local) ++p;
+            const int ci = (int)(local - p * n_ic);
+            const int64_t P = RAC_DF(n_sets);
+            n_genes = RAC_DF(n_genes);
+            const int stride = RAC_DF(stride);
+            const int32_t* lane_edge = RAC_DF(lane_edge) + r * stride;
+            const float* Tp = RAC_DF(T) + p;
+            const float* Lp = RAC_DF(lam) + p;
+            const uint8_t* Np = RAC_DF(n) + p;
+#pragma unroll
+            for (int s = 0; s < EPL; ++s) {
+                asm volatile("" ::: "memory");
+                const int pk = s < stride ? lane_edge[s] : -1;
+                if (pk >= 0) {
+                    const int e = pk & 0xffff, src = pk >> 16;
+                    const R Tv = (R)Tp[e * P];
+                    const R sl = O::sqrt((R)Lp[e * P]);
+                    e_xa[s] = (wave_elem + (uint32_t)(src * n_groups + g)) * SZ;
+                    e_invT[s] = (R)1 / Tv;
+                    e_n[s] = O::to_n((int)Np[e * P]);
+                    e_b[s] = sl;
+                    e_d[s] = (R)1 / sl - sl;
+                } else {
+                    e_xa[s] = sink; e_invT[s] = 0; e_b[s] = 1; e_d[s] = 0; e_n[s] = O::to_n(1);
+                }
+            }
+            const float* Gp = RAC_DF(G) + p;
+            const float* Kp = RAC_DF(k) + p;
+            const float* icp = RAC_DF(ic) + (int64_t)ci * n_genes;
+            const int32_t* row_ptr = RAC_DF(row_ptr);
+            const int32_t* gene_row = RAC_DF(gene_row);
+            const int8_t* sign = RAC_DF(sign);
+#undef RAC_DF
+#pragma unroll
+            for (int q = 0; q < GPL; ++q) {
+                asm volatile("" ::: "memory");
+                const int gene = r + q * lpt;
+                if (gene < n_genes) {
+                    const R Gv = (R)Gp[gene * P];
+                    const R kv = (R)Kp[gene * P];
+                    // Fold each row's sqrt(lam) (and, for activation
+                    // over lambda, 1/lam) into the production rate.
+                    R gf = Gv;
+                    for (int e = row_ptr[gene]; e < row_ptr[gene + 1]; ++e) {
+                        const R sl = O::sqrt((R)Lp[e * P]);
+                        gf *= (sign[e] > 0 && c.divide) ? (R)1 / sl : sl;
+                    }
+                    const int row = gene_row[gene];
+                    const int rl = row & 0xff, pb = (row >> 8) & 0xff, pe = (row >> 16) & 0xff;
+                    const uint32_t rowlane = (uint32_t)(gshift + rl);
+                    g_id[q] = gene;
+                    g_wa[q] = (wave_elem + (uint32_t)(gene * n_groups + g)) * SZ;
+                    g_pb[q] = (wave_elem + 64 * GPL + (uint32_t)pb * 64 + rowlane) * SZ;
+                    g_pe[q] = (wave_elem + 64 * GPL + (uint32_t)pe * 64 + rowlane) * SZ;
+                    gG[q] = gf;
+                    gk[q] = kv;
+                    const R u = (R)icp[gene];
+                    x[q] = c.ic_absolute ? u : u * Gv / kv;
+                } else {
+                    g_id[q] = -1; g_wa[q] = sink; g_pb[q] = pre_base; g_pe[q] = pre_base;
+                    gG[q] = 0; gk[q] = 0; x[q] = 0;
+                }
+            }
+            t = c.t0;
+            t_stop = TS ? a.t_out[a.n_t - 1] : c.t_end;
+            nacc = 0; nrej = 0; kout = 0; last_rej = false;
+            fresh = true;
+    };
+
+    auto save = [&]() {
+        reinterpret_cast<int64_t*>(sbase + kOffTraj)[lane] = traj;
+#pragma unroll
+        for (int q = 0; q < GPL; ++q) {
+            reinterpret_cast<R*>(sbase)[q * 64 + lane] = x[q];
+            reinterpret_cast<R*>(sbase + kOffK)[q * 64 + lane] = kk[0][q];
+        }
+        reinterpret_cast<double*>(sbase + kOffT)[lane] = t;
+        reinterpret_cast<double*>(sbase + kOffH)[lane] = h;
+        reinterpret_cast<int32_t*>(sbase + kOffAcc)[lane] = nacc;
+        reinterpret_cast<int32_t*>(sbase + kOffRej)[lane] = nrej;
+        reinterpret_cast<int32_t*>(sbase + kOffFlags)[lane] = (last_rej ? 1 : 0) | (fresh ? 2 : 0);
+    };
+
+    if (BOUNDED) {
+        // Resume the trajectories this wave held when the previous batch ended.
+        const int64_t saved = reinterpret_cast<const int64_t*>(sbase + kOffTraj)[lane];
+        if (saved >= 0) {
+            load_traj(saved);
+#pragma unroll
+            for (int q = 0; q < GPL; ++q) {
+                x[q] = reinterpret_cast<const R*>(sbase)[q * 64 + lane];
+                kk[0][q] = reinterpret_cast<const R*>(sbase + kOffK)[q * 64 + lane];
+            }
+            t = reinterpret_cast<const double*>(sbase + kOffT)[lane];
+            h = reinterpret_cast<const double*>(sbase + kOffH)[lane];
+            nacc = reinterpret_cast<const int32_t*>(sbase + kOffAcc)[lane];
+            nrej = reinterpret_cast<const int32_t*>(sbase + kOffRej)[lane];
+            const int32_t fl = reinterpret_cast<const int32_t*>(sbase + kOffFlags)[lane];
+            last_rej = (fl & 1) != 0;
+            fresh = (fl & 2) != 0;
+        }
+    }
+
+    for (int iter = 0;; ++iter) {
+        if (BOUNDED && iter >= a.batch_steps) {
+            save();
+            return;
+        }
         // ---- refill free groups from the work queue --------------------
         if (!exhausted) {
             const uint64_t free_lead = __ballot(traj < 0 && r == 0);
             const int nfree = __popcll(free_lead);
             const uint64_t busy_lead = __ballot(traj >= 0 && r == 0);
+            const uint64_t total =
+                BOUNDED ? __hip_atomic_load(&a.ctl->total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                        : (uint64_t)a.total;
             // Refill in batches (each refill costs the wave two extra right-hand
             // sides), but take single items once the queue is nearly drained.
-            const bool near_end = (uint64_t)a.total - popped < (uint64_t)gridDim.x * (kBlock / 64) * 64;
+            const bool near_end = popped >= total ||
+                                  total - popped < (uint64_t)gridDim.x * (kBlock / 64) * 64;
             if (nfree > 0 && (nfree >= c.refill_min || busy_lead == 0 || near_end)) {
-                unsigned long long base = 0;
-                if (lane == 0) base = atomicAdd(a.counter, (unsigned long long)nfree);
+                unsigned long long base = 0, got = 0;
+                if (lane == 0) {
+                    if (BOUNDED) {
+                        // The host may append work between launches, so never
+                        // move head past total: claim [head, min(head + nfree, total)).
+                        unsigned long long head =
+                            __hip_atomic_load(&a.ctl->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        for (;;) {
+                            if (head >= total) {
+                                base = head;
+                                got = 0;
+                                break;
+                            }
+                            const unsigned long long want =
+                                head + (unsigned long long)nfree < total ? head + nfree : total;
+                            const unsigned long long old = atomicCAS(&a.ctl->head, head, want);
+                            if (old == head) {
+                                base = head;
+                                got = want - head;
+                                break;
+                            }
+                            head = old;
+                        }
+                    } else {
+                        base = atomicAdd(a.counter, (unsigned long long)nfree);
+                        got = (unsigned long long)nfree;
+                    }
+                }
                 base = __shfl(base, 0);
-                popped = base + (unsigned long long)nfree;
-                if (base + (unsigned long long)nfree >= (unsigned long long)a.total) exhausted = true;
+                got = __shfl(got, 0);
+                popped = base + got;
+                if (base + (unsigned long long)nfree >= total || got < (unsigned long long)nfree)
+                    exhausted = true;
                 if (traj < 0) {
                     const int rank = __popcll(free_lead & ((1ull << gshift) - 1ull));
                     const int64_t idx = (int64_t)base + rank;
-                    if (idx < a.total) {
-                        // Which network: binary search over first queue indices.
-                        net = 0;
-                        if (a.nets) {
-                            int lo = 0, hi = a.n_nets - 1;
-                            while (lo < hi) {
-                                const int mid = (lo + hi + 1) >> 1;
-                                if (a.nets[mid].traj_begin <= idx) lo = mid; else hi = mid - 1;
-                            }
-                            net = lo;
-                        }
-                        // Loads go one slot at a time (the memory clobbers stop
-                        // the scheduler from hoisting them all), which keeps
-                        // this rarely taken path from setting the kernel's
-                        // register peak next to the live trajectory state.
-                        const NetDesc* dp = a.nets ? a.nets + net : nullptr;
-#define RAC_DF(field) (dp ? dp->field : a.net0.field)
-                        traj = idx;
-                        local = idx - RAC_DF(traj_begin);
-                        const int n_ic = RAC_DF(n_ic);
-                        int64_t p = (int64_t)((double)local * RAC_DF(inv_n_ic));
-                        if (p * n_ic > local) --p;
-                        if ((p + 1) * n_ic <= local) ++p;
-                        const int ci = (int)(local - p * n_ic);
-                        const int64_t P = RAC_DF(n_sets);
-                        n_genes = RAC_DF(n_genes);
-                        const int stride = RAC_DF(stride);
-                        const int32_t* lane_edge = RAC_DF(lane_edge) + r * stride;
-                        const float* Tp = RAC_DF(T) + p;
-                        const float* Lp = RAC_DF(lam) + p;
-                        const uint8_t* Np = RAC_DF(n) + p;
-#pragma unroll
-                        for (int s = 0; s < EPL; ++s) {
-                            asm volatile("" ::: "memory");
-                            const int pk = s < stride ? lane_edge[s] : -1;
-                            if (pk >= 0) {
-                                const int e = pk & 0xffff, src = pk >> 16;
-                                const R Tv = (R)Tp[e * P];
-                                const R sl = O::sqrt((R)Lp[e * P]);
-                                e_xa[s] = (wave_elem + (uint32_t)(src * n_groups + g)) * SZ;
-                                e_invT[s] = (R)1 / Tv;
-                                e_n[s] = O::to_n((int)Np[e * P]);
-                                e_b[s] = sl;
-                                e_d[s] = (R)1 / sl - sl;
-                            } else {
-                                e_xa[s] = sink; e_invT[s] = 0; e_b[s] = 1; e_d[s] = 0; e_n[s] = O::to_n(1);
-                            }
-                        }
-                        const float* Gp = RAC_DF(G) + p;
-                        const float* Kp = RAC_DF(k) + p;
-                        const float* icp = RAC_DF(ic) + (int64_t)ci * n_genes;
-                        const int32_t* row_ptr = RAC_DF(row_ptr);
-                        const int32_t* gene_row = RAC_DF(gene_row);
-                        const int8_t* sign = RAC_DF(sign);
-#undef RAC_DF
-#pragma unroll
-                        for (int q = 0; q < GPL; ++q) {
-                            asm volatile("" ::: "memory");
-                            const int gene = r + q * lpt;
-                            if (gene < n_genes) {
-                                const R Gv = (R)Gp[gene * P];
-                                const R kv = (R)Kp[gene * P];
-                                // Fold each row's sqrt(lam) (and, for activation
-                                // over lambda, 1/lam) into the production rate.
-                                R gf = Gv;
-                                for (int e = row_ptr[gene]; e < row_ptr[gene + 1]; ++e) {
-                                    const R sl = O::sqrt((R)Lp[e * P]);
-                                    gf *= (sign[e] > 0 && c.divide) ? (R)1 / sl : sl;
-                                }
-                                const int row = gene_row[gene];
-                                const int rl = row & 0xff, pb = (row >> 8) & 0xff, pe = (row >> 16) & 0xff;
-                                const uint32_t rowlane = (uint32_t)(gshift + rl);
-                                g_id[q] = gene;
-                                g_wa[q] = (wave_elem + (uint32_t)(gene * n_groups + g)) * SZ;
-                                g_pb[q] = (wave_elem + 64 * GPL + (uint32_t)pb * 64 + rowlane) * SZ;
-                                g_pe[q] = (wave_elem + 64 * GPL + (uint32_t)pe * 64 + rowlane) * SZ;
-                                gG[q] = gf;
-                                gk[q] = kv;
-                                const R u = (R)icp[gene];
-                                x[q] = c.ic_absolute ? u : u * Gv / kv;
-                            } else {
-                                g_id[q] = -1; g_wa[q] = sink; g_pb[q] = pre_base; g_pe[q] = pre_base;
-                                gG[q] = 0; gk[q] = 0; x[q] = 0;
-                            }
-                        }
-                        t = c.t0;
-                        t_stop = TS ? a.t_out[a.n_t - 1] : c.t_end;
-                        nacc = 0; nrej = 0; kout = 0; last_rej = false;
-                        fresh = true;
-                    }
+                    if ((unsigned long long)rank < got && (uint64_t)idx < total) load_traj(idx);
                 }
             }
         }
         if (__ballot(traj >= 0) == 0) {
-            if (exhausted) break;
+            if (exhausted) {
+                if (BOUNDED) save();
+                break;
+            }
             continue;
         }
 

@@ -37,6 +37,7 @@ struct NetDesc {
     int8_t* status;
     int32_t* n_acc;
     int32_t* n_rej;
+    int32_t* done;             // finished-trajectory counter (serving), or nullptr
     int64_t n_sets;            // parameter array stride P
     int64_t traj_begin;        // first queue index of this network
     int64_t n_traj;            // P * n_ic
@@ -50,6 +51,16 @@ struct Controls {
     int32_t divide, ic_absolute, stop_at_steady, refill_min;
 };
 
+// Device-resident queue control of a serving step batch: the kernel pops
+// [head, total); the host appends work by raising total and n_nets between
+// batches and never writes head.
+struct ServeCtl {
+    unsigned long long head;
+    unsigned long long total;
+    int32_t n_nets;
+    int32_t pad;
+};
+
 struct LaunchArgs {
     const NetDesc* nets;  // device array when n_nets > 1, else nullptr
     NetDesc net0;         // the network when nets == nullptr
@@ -60,8 +71,16 @@ struct LaunchArgs {
     const double* t_out;    // device, time-series mode
     int32_t n_t;
     Controls c;
+    // Serving step batches only.
+    ServeCtl* ctl;          // queue control in device memory
+    char* slots;            // per-wave saved trajectory state
+    int32_t batch_steps;    // loop iterations per launch
 };
 
 constexpr int kBlock = 256;  // 4 independent waves per block
+
+// Bytes of saved state per wave between serving step batches (x and k1 per
+// gene slot, then t, h, trajectory id, step counts and flags per lane).
+constexpr size_t serve_slot_bytes(int gpl, size_t elem) { return (size_t)128 * gpl * elem + 2304; }
 
 }  // namespace rac

@@ -11,6 +11,7 @@ struct KernelEntry {
     int precision;  // RAC_FP32 / RAC_FP64
     bool ts;        // time-series mode
     int epl, gpl;   // compiled slot budgets
+    bool bounded;   // serving step-batch variant
     const void* fn; // __global__ function
 };
 
@@ -19,7 +20,8 @@ int kernels_f32_ss(const KernelEntry** out);
 int kernels_f32_ts(const KernelEntry** out);
 int kernels_f64_ss(const KernelEntry** out);
 int kernels_f64_ts(const KernelEntry** out);
+int kernels_f32_serve(const KernelEntry** out);
 
-const KernelEntry* find_kernel(int precision, bool ts, int epl, int gpl);
+const KernelEntry* find_kernel(int precision, bool ts, int epl, int gpl, bool bounded = false);
 
 }  // namespace rac

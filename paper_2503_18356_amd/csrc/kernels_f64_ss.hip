@@ -5,7 +5,7 @@
 
 namespace rac {
 
-#define RAC_K(E, G) {RAC_FP64, false, E, G, reinterpret_cast<const void*>(&dp5_kernel<double, E, G, false>)}
+#define RAC_K(E, G) {RAC_FP64, false, E, G, false, reinterpret_cast<const void*>(&dp5_kernel<double, E, G, false>)}
 
 static const KernelEntry kTable[] = {
     RAC_K(4, 1), RAC_K(4, 2), RAC_K(4, 3), RAC_K(4, 4), RAC_K(4, 6), RAC_K(8, 1), RAC_K(8, 2),

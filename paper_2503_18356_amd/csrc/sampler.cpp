@@ -82,6 +82,10 @@ bool ranges_ok(const rac_ranges& r) {
 }
 
 }  // namespace
+
+bool sample_ranges_ok(const rac_ranges& r) { return ranges_ok(r); }
+double sample_ratio_median(const rac_ranges& r) { return ratio_median(r); }
+
 }  // namespace rac
 
 extern "C" {

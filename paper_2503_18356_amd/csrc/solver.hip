@@ -22,10 +22,10 @@ namespace rac {
             return fail(RAC_EDEVICE, std::string(what) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-const KernelEntry* find_kernel(int precision, bool ts, int epl, int gpl) {
+const KernelEntry* find_kernel(int precision, bool ts, int epl, int gpl, bool bounded) {
     static std::vector<KernelEntry> all = [] {
         std::vector<KernelEntry> v;
-        for (auto fn : {kernels_f32_ss, kernels_f32_ts, kernels_f64_ss, kernels_f64_ts}) {
+        for (auto fn : {kernels_f32_ss, kernels_f32_ts, kernels_f64_ss, kernels_f64_ts, kernels_f32_serve}) {
             const KernelEntry* t = nullptr;
             int n = fn(&t);
             v.insert(v.end(), t, t + n);
@@ -33,8 +33,23 @@ const KernelEntry* find_kernel(int precision, bool ts, int epl, int gpl) {
         return v;
     }();
     for (const KernelEntry& k : all)
-        if (k.precision == precision && k.ts == ts && k.epl == epl && k.gpl == gpl) return &k;
+        if (k.precision == precision && k.ts == ts && k.epl == epl && k.gpl == gpl && k.bounded == bounded)
+            return &k;
     return nullptr;
+}
+
+// A library-owned non-blocking stream per device for small uploads, so that
+// building a plan never waits for (or serialises with) work on user streams.
+static hipStream_t lib_stream(int dev) {
+    static std::mutex m;
+    static std::map<int, hipStream_t> streams;
+    std::lock_guard<std::mutex> lk(m);
+    auto it = streams.find(dev);
+    if (it != streams.end()) return it->second;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+    streams[dev] = s;
+    return s;
 }
 
 rac_status get_device_plan(const rac_topology* t, int lpt, const DevicePlan** out) {
@@ -49,18 +64,20 @@ rac_status get_device_plan(const rac_topology* t, int lpt, const DevicePlan** ou
         }
     const size_t n_le = lp->lane_edge.size(), N = t->n_genes, E = t->n_edges;
     const size_t bytes = 4 * (n_le + N + N + 1) + std::max<size_t>(E, 1);
+    hipStream_t ls = lib_stream(dev);
+    if (!ls) return fail(RAC_EDEVICE, "device plan: no upload stream");
     void* block = nullptr;
-    if (hipMalloc(&block, bytes) != hipSuccess)
-        return fail(RAC_ENOMEM, "device plan: hipMalloc failed");
+    if (hipMallocAsync(&block, bytes, ls) != hipSuccess) return fail(RAC_ENOMEM, "device plan: allocation failed");
     std::vector<char> host(bytes, 0);
     char* h = host.data();
     std::memcpy(h, lp->lane_edge.data(), 4 * n_le);
     std::memcpy(h + 4 * n_le, lp->gene_row.data(), 4 * N);
     std::memcpy(h + 4 * (n_le + N), t->row_ptr.data(), 4 * (N + 1));
     if (E) std::memcpy(h + 4 * (n_le + 2 * N + 1), t->sign.data(), E);
-    if (hipMemcpy(block, h, bytes, hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(block);
-        return fail(RAC_EDEVICE, "device plan: hipMemcpy failed");
+    if (hipMemcpyAsync(block, h, bytes, hipMemcpyHostToDevice, ls) != hipSuccess ||
+        hipStreamSynchronize(ls) != hipSuccess) {
+        (void)hipFreeAsync(block, ls);
+        return fail(RAC_EDEVICE, "device plan: upload failed");
     }
     DevicePlan d;
     d.device = dev;
@@ -76,13 +93,13 @@ rac_status get_device_plan(const rac_topology* t, int lpt, const DevicePlan** ou
     return RAC_OK;
 }
 
+// Plans are released on the upload stream without a device-wide
+// synchronisation; the caller guarantees no enqueued work still reads them.
 void free_device_plans(rac_topology* t) {
-    int cur = 0;
-    bool have_cur = hipGetDevice(&cur) == hipSuccess;
     for (auto& d : t->dev_plans) {
-        if (hipSetDevice(d.device) == hipSuccess) (void)hipFree(d.block);
+        hipStream_t ls = lib_stream(d.device);
+        if (ls) (void)hipFreeAsync(d.block, ls);
     }
-    if (have_cur) (void)hipSetDevice(cur);
     t->dev_plans.clear();
 }
 
@@ -178,6 +195,7 @@ rac_status launch_group(const std::vector<Job>& jobs, int lpt, const rac_solver_
         rac_status st = get_device_plan(j.topo, lpt, &dp);
         if (st != RAC_OK) return st;
         NetDesc d;
+        std::memset(&d, 0, sizeof(d));
         d.lane_edge = dp->lane_edge;
         d.gene_row = dp->gene_row;
         d.row_ptr = dp->row_ptr;
@@ -298,6 +316,14 @@ rac_status run_jobs(std::vector<Job>& jobs, const rac_solver_opts* o, bool ts,
 }
 
 }  // namespace
+
+rac_status check_opts_public(const rac_solver_opts* o, const char* who) { return check_opts(o, who); }
+rac_status check_item_public(const rac_topology* topo, const rac_params_view* p, const float* ic,
+                             int32_t n_ic, const void* x_out, const char* who) {
+    return check_item(topo, p, ic, n_ic, x_out, who);
+}
+Controls make_controls_public(const rac_solver_opts* o, int n_groups) { return make_controls(o, n_groups); }
+
 }  // namespace rac
 
 extern "C" {

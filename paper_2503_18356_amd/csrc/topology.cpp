@@ -206,6 +206,19 @@ int32_t rac_auto_lanes(const rac_topology* topo, int32_t precision) {
     return rac::auto_lanes(topo, precision);
 }
 
+rac_status rac_plan_shape(const rac_topology* topo, int32_t precision, int32_t lanes, int32_t* epl,
+                          int32_t* gpl) {
+    if (!topo || (precision != RAC_FP32 && precision != RAC_FP64))
+        return rac::fail(RAC_EINVAL, "rac_plan_shape: bad topology or precision");
+    if (!rac::plan_fits(topo, lanes, precision))
+        return rac::fail(RAC_EUNSUPPORTED, "rac_plan_shape: no compiled shape for this lane count");
+    const rac::LanePlan* p = rac::get_plan(topo, lanes);
+    const rac::Shape s = rac::pick_shape(std::max(p->epl, 1), p->gpl, precision);
+    if (epl) *epl = s.epl;
+    if (gpl) *gpl = s.gpl;
+    return RAC_OK;
+}
+
 int32_t rac_lanes_supported(const rac_topology* topo, int32_t precision, int32_t lanes) {
     if (!topo || (precision != RAC_FP32 && precision != RAC_FP64)) return 0;
     return rac::plan_fits(topo, lanes, precision) ? 1 : 0;

@@ -100,6 +100,23 @@ def lib():
         L.rac_auto_lanes.restype = i32
         L.rac_lanes_supported.argtypes = [vp, i32, i32]
         L.rac_lanes_supported.restype = i32
+        L.rac_plan_shape.argtypes = [vp, i32, i32, vp, vp]
+        L.rac_plan_shape.restype = C.c_int
+        L.rac_sample_params_device.argtypes = [vp, C.POINTER(_Ranges), C.c_uint64, i64, i64, i32,
+                                               C.POINTER(_ParamsView), vp, vp]
+        L.rac_sample_params_device.restype = C.c_int
+        L.rac_server_create.argtypes = [C.POINTER(_Opts), i32, i32, i32, i32, C.POINTER(vp)]
+        L.rac_server_create.restype = C.c_int
+        L.rac_server_destroy.argtypes = [vp]
+        L.rac_server_submit.argtypes = [vp, vp, C.POINTER(_ParamsView), vp, i32, vp,
+                                        C.POINTER(_Info), vp, C.POINTER(i32)]
+        L.rac_server_submit.restype = C.c_int
+        L.rac_server_step.argtypes = [vp, vp]
+        L.rac_server_step.restype = C.c_int
+        L.rac_server_done_counts.argtypes = [vp, i32, i32, vp, vp]
+        L.rac_server_done_counts.restype = C.c_int
+        L.rac_server_info.argtypes = [vp, vp, vp, vp, vp]
+        L.rac_server_info.restype = C.c_int
         _lib = L
     return _lib
 
@@ -145,6 +162,12 @@ class Topology:
 
     def lanes_supported(self, lanes: int, precision: int = FP32) -> bool:
         return bool(lib().rac_lanes_supported(self._h, precision, lanes))
+
+    def shape(self, lanes: int, precision: int = FP32) -> tuple[int, int]:
+        """Compiled (edge slots, gene slots) per lane at this lane count."""
+        e, g = C.c_int32(), C.c_int32()
+        _check(lib().rac_plan_shape(self._h, precision, lanes, C.byref(e), C.byref(g)))
+        return e.value, g.value
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -234,6 +257,27 @@ def sample_params(topo: Topology, seed: int, n_sets: int, n_ic: int, set_begin: 
     _check(lib().rac_sample_params(topo.handle, C.byref(rr), C.c_uint64(seed & (2**64 - 1)),
                                    set_begin, P, n_ic, C.byref(v), ic.ctypes.data))
     return HostParams(G, k, T, lam, n, ic)
+
+
+def alloc_params(topo: Topology, n_sets: int, n_ic: int, device="cuda") -> DeviceParams:
+    import torch
+    N, E, P = topo.n_genes, topo.n_edges, int(n_sets)
+    f = lambda *sh: torch.empty(sh, dtype=torch.float32, device=device)
+    return DeviceParams(f(N, P), f(N, P), f(E, P), f(E, P),
+                        torch.empty((E, P), dtype=torch.uint8, device=device), f(n_ic, N))
+
+
+def sample_params_device(topo: Topology, seed: int, n_sets: int, n_ic: int, set_begin: int = 0,
+                         ranges: Ranges | None = None, out: DeviceParams | None = None,
+                         stream=None) -> DeviceParams:
+    """rac_sample_params_device: the same draws as sample_params, on the GPU."""
+    out = out or alloc_params(topo, n_sets, n_ic)
+    v = out.view()
+    rr = (ranges or Ranges()).c()
+    _check(lib().rac_sample_params_device(topo.handle, C.byref(rr), C.c_uint64(seed & (2**64 - 1)),
+                                          set_begin, int(n_sets), n_ic, C.byref(v),
+                                          out.ic.data_ptr(), _stream_ptr(stream)))
+    return out
 
 
 @dataclass
@@ -340,3 +384,48 @@ def steady_states_batch(items, opts: Opts | None = None, stream=None) -> list[Re
     o = opts.c()
     _check(lib().rac_steady_states_batch(arr, len(items), C.byref(o), _stream_ptr(stream)))
     return outs
+
+
+class StepServer:
+    """One rac_server: step batches of the bounded kernel for networks that fit
+    (lanes, epl, gpl)."""
+
+    def __init__(self, opts: Opts, lanes: int, epl: int, gpl: int, max_requests: int = 65536,
+                 batch_steps: int = 256):
+        o = Opts(**{f.name: getattr(opts, f.name) for f in fields(opts)})
+        o.lanes_per_traj = lanes
+        h = C.c_void_p()
+        _check(lib().rac_server_create(C.byref(o.c()), epl, gpl, max_requests, batch_steps,
+                                       C.byref(h)))
+        self._h = h
+        self.lanes, self.epl, self.gpl = lanes, epl, gpl
+        self.n_requests = 0
+
+    def submit(self, topo: Topology, params: DeviceParams, out: Result, stream=None) -> int:
+        v = params.view()
+        info = _info(out)
+        rid = C.c_int32()
+        _check(lib().rac_server_submit(self._h, topo.handle, C.byref(v), params.ic.data_ptr(),
+                                       params.n_ic, out.x.data_ptr(), C.byref(info),
+                                       _stream_ptr(stream), C.byref(rid)))
+        self.n_requests = rid.value + 1
+        return rid.value
+
+    def step(self, stream=None):
+        _check(lib().rac_server_step(self._h, _stream_ptr(stream)))
+
+    def done_counts(self, first: int, count: int, out: np.ndarray, stream=None):
+        """Enqueue the copy of finished counts into out[:count] (int32, host)."""
+        _check(lib().rac_server_done_counts(self._h, first, count, out.ctypes.data,
+                                            _stream_ptr(stream)))
+
+    def info(self) -> dict:
+        n, tot, waves, sb = C.c_int32(), C.c_int64(), C.c_int32(), C.c_int64()
+        _check(lib().rac_server_info(self._h, C.byref(n), C.byref(tot), C.byref(waves), C.byref(sb)))
+        return dict(n_requests=n.value, total=tot.value, waves=waves.value, slot_bytes=sb.value)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.rac_server_destroy(h)
+            self._h = None

@@ -1,0 +1,222 @@
+"""Continuous-batching serving loop for RACIPE simulation requests.
+
+A request is (network, seed, parameter sets P, initial conditions n_ic): the
+steady states of all P * n_ic trajectories (GRiNS Sec. 2.1.3).  Requests
+arrive over time; the scheduler admits them while their device footprint fits
+the HBM budget, samples their parameters on the GPU, and hands them to a
+per-kernel-class step server (rac_server_*): every step batch advances all
+in-flight trajectories of every admitted request of that class, so requests
+that arrive while others run share the same launches.  Finished requests
+release their memory, which admits waiting ones.  Latency is measured from
+arrival to the host seeing the request's last trajectory finish.
+
+The scheduler talks to an executor (``GpuExecutor`` here); tests drive it
+with a CPU stand-in to check admission, ordering and accounting.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    rid: int
+    topo: object          # inputs.Topology
+    seed: int
+    n_sets: int
+    n_ic: int
+    arrival: float = 0.0  # seconds (scheduler clock)
+    admitted: float = -1.0
+    finished: float = -1.0
+    nbytes: int = 0
+    result: object = None
+    handle: object = None  # executor-private
+
+    @property
+    def n_traj(self) -> int:
+        return self.n_sets * self.n_ic
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+def footprint_bytes(n_genes: int, n_edges: int, n_sets: int, n_ic: int, x_bytes: int = 4) -> int:
+    """Device bytes a request holds while admitted: parameters, initial
+    conditions, steady states and per-trajectory info."""
+    params = n_sets * (2 * n_genes * 4 + 2 * n_edges * 4 + n_edges)
+    ics = n_ic * n_genes * 4
+    outs = n_sets * n_ic * (n_genes * x_bytes + 8 + 1 + 4 + 4)
+    return int(params + ics + outs)
+
+
+class Scheduler:
+    """Admission by HBM footprint, continuous batching, latency accounting."""
+
+    def __init__(self, executor, hbm_budget: int, clock=time.perf_counter):
+        self.ex = executor
+        self.budget = int(hbm_budget)
+        self.used = 0
+        self.clock = clock
+        self.waiting: collections.deque[Request] = collections.deque()
+        self.running: dict[int, Request] = {}
+        self.done: list[Request] = []
+        self.rejected: list[Request] = []
+        self.t0 = clock()
+
+    def now(self) -> float:
+        return self.clock() - self.t0
+
+    def arrive(self, req: Request):
+        req.arrival = self.now() if req.arrival <= 0 else req.arrival
+        req.nbytes = footprint_bytes(req.topo.n_genes, req.topo.n_edges, req.n_sets, req.n_ic)
+        if req.nbytes > self.budget:
+            self.rejected.append(req)  # can never fit
+            return
+        self.waiting.append(req)
+
+    def admit(self):
+        # First come, first served: a large request at the head waits for
+        # memory rather than being overtaken indefinitely.
+        while self.waiting and self.used + self.waiting[0].nbytes <= self.budget:
+            req = self.waiting.popleft()
+            self.used += req.nbytes
+            req.admitted = self.now()
+            self.ex.start(req)
+            self.running[req.rid] = req
+
+    def step(self):
+        if self.running:
+            self.ex.step()
+            for rid in self.ex.finished():
+                req = self.running.pop(rid)
+                req.finished = self.now()
+                self.ex.release(req)
+                self.used -= req.nbytes
+                self.done.append(req)
+
+    def idle(self) -> bool:
+        return not self.waiting and not self.running
+
+    def run(self, arrivals: list[Request], until_idle: bool = True, max_seconds: float = 600.0):
+        """Feed requests at their arrival times (seconds from now) and serve."""
+        pending = sorted(arrivals, key=lambda r: r.arrival)
+        i = 0
+        self.t0 = self.clock()
+        while True:
+            now = self.now()
+            while i < len(pending) and pending[i].arrival <= now:
+                self.arrive(pending[i])
+                i += 1
+            self.admit()
+            if self.running:
+                self.step()
+            elif i < len(pending):
+                time.sleep(min(0.001, max(0.0, pending[i].arrival - self.now())))
+            if i >= len(pending) and self.idle():
+                break
+            if self.now() > max_seconds:
+                raise TimeoutError("serving did not drain in time")
+        return self.done
+
+    def stats(self, skip: int = 0) -> dict:
+        reqs = sorted(self.done, key=lambda r: r.rid)[skip:]
+        if not reqs:
+            return {}
+        lat = np.array([r.latency for r in reqs])
+        t_first = min(r.arrival for r in reqs)
+        t_last = max(r.finished for r in reqs)
+        solves = sum(r.n_traj for r in reqs)
+        return {"requests": len(reqs), "solves": int(solves),
+                "solves_per_s": solves / max(t_last - t_first, 1e-9),
+                "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "mean_ms": float(lat.mean() * 1e3), "rejected": len(self.rejected)}
+
+
+class GpuExecutor:
+    """Runs admitted requests on the GPU through rac_server step batches, one
+    server (and stream) per kernel class (lanes per trajectory, slot shape)."""
+
+    def __init__(self, opts=None, batch_steps: int = 256, max_requests: int = 65536,
+                 device="cuda", keep_results: bool = True):
+        import torch
+        from . import racipe as rp
+        self.rp = rp
+        self.torch = torch
+        self.opts = opts or rp.Opts(precision=rp.FP32)
+        self.batch_steps = batch_steps
+        self.max_requests = max_requests
+        self.device = device
+        self.keep_results = keep_results
+        self.classes: dict[tuple, dict] = {}
+        self.topo_cache: dict[int, object] = {}
+
+    def _class(self, T):
+        lanes = T.auto_lanes(self.rp.FP32)
+        epl, gpl = T.shape(lanes, self.rp.FP32)
+        key = (lanes, epl, gpl)
+        if key not in self.classes:
+            srv = self.rp.StepServer(self.opts, lanes, epl, gpl, self.max_requests, self.batch_steps)
+            self.classes[key] = {"server": srv, "stream": self.torch.cuda.Stream(device=self.device),
+                                 "active": {}, "counts": np.zeros(self.max_requests, np.int32)}
+        return key, self.classes[key]
+
+    def start(self, req: Request):
+        rp = self.rp
+        T = rp.Topology.from_inputs(req.topo)
+        key, cl = self._class(T)
+        stream = cl["stream"]
+        with self.torch.cuda.stream(stream):
+            params = rp.alloc_params(T, req.n_sets, req.n_ic, device=self.device)
+            rp.sample_params_device(T, req.seed, req.n_sets, req.n_ic, out=params, stream=stream)
+            res = rp.alloc_result(req.n_traj, T.n_genes, rp.FP32, device=self.device)
+        srv_rid = cl["server"].submit(T, params, res, stream=stream)
+        req.handle = {"class": key, "srv_rid": srv_rid, "T": T, "params": params}
+        req.result = res
+        cl["active"][srv_rid] = req
+
+    def step(self):
+        for cl in self.classes.values():
+            if cl["active"]:
+                cl["server"].step(stream=cl["stream"])
+
+    def finished(self) -> list[int]:
+        out = []
+        for cl in self.classes.values():
+            act = cl["active"]
+            if not act:
+                continue
+            lo, hi = min(act), max(act) + 1
+            cl["server"].done_counts(lo, hi - lo, cl["counts"], stream=cl["stream"])
+            cl["stream"].synchronize()
+            for srv_rid in list(act):
+                req = act[srv_rid]
+                if cl["counts"][srv_rid - lo] >= req.n_traj:
+                    out.append(req.rid)
+                    del act[srv_rid]
+        return out
+
+    def release(self, req: Request):
+        # Parameters go; the result tensors stay with the request unless the
+        # caller only wants throughput and latency.
+        req.handle["params"] = None
+        if not self.keep_results:
+            req.result = None
+
+
+def poisson_requests(rng, n: int, rate: float, n_lo=2, n_hi=100, p_lo=100, p_hi=100000,
+                     ic_lo=1, ic_hi=10, seed0: int = 5000) -> list[Request]:
+    """Poisson arrivals of random networks with log-uniform sizes."""
+    from . import inputs
+    t = 0.0
+    out = []
+    for i in range(n):
+        t += rng.exponential(1.0 / rate)
+        topo, P, n_ic = inputs.serving_request(rng, n_lo, n_hi, p_lo, p_hi, ic_lo, ic_hi)
+        out.append(Request(i, topo, seed0 + i, P, n_ic, arrival=t))
+    return out

@@ -1,0 +1,146 @@
+"""GPU: device sampling, serving step batches and continuous batching.
+
+A trajectory's result must not depend on how it was scheduled: alone or in
+a mix, in one launch or parked and resumed across many step batches, it is
+bit-identical to rac_steady_states with the same lane count.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_18356_amd import inputs
+from paper_2503_18356_amd import racipe as rp
+from paper_2503_18356_amd.serve import GpuExecutor, Request, Scheduler, poisson_requests
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("topo,seed", [(inputs.toggle_switch(), 1), (inputs.dense_core(1004), 7),
+                                       (inputs.erdos_renyi(100, 250, 3), 11)])
+def test_device_sampler_is_bit_identical(topo, seed):
+    T = rp.Topology.from_inputs(topo)
+    for begin, P, n_ic in [(0, 1000, 7), (123456, 77, 3)]:
+        h = rp.sample_params(T, seed, P, n_ic, set_begin=begin)
+        d = rp.sample_params_device(T, seed, P, n_ic, set_begin=begin)
+        torch.cuda.synchronize()
+        for f in ("G", "k", "T", "lam", "n", "ic"):
+            assert np.array_equal(getattr(h, f), getattr(d, f).cpu().numpy()), f
+
+
+def test_device_sampler_custom_ranges():
+    T = rp.Topology.from_inputs(inputs.erdos_renyi(8, 14, 2))
+    r = rp.Ranges(g_min=1, g_max=10, k_min=0.01, k_max=1, n_min=2, n_max=4, lam_inh_min=0.1)
+    h = rp.sample_params(T, 5, 300, 2, ranges=r)
+    d = rp.sample_params_device(T, 5, 300, 2, ranges=r)
+    torch.cuda.synchronize()
+    for f in ("G", "k", "T", "lam", "n", "ic"):
+        assert np.array_equal(getattr(h, f), getattr(d, f).cpu().numpy()), f
+
+
+def _direct(T, params, lanes):
+    out = rp.steady_states(T, params, rp.Opts(precision=rp.FP32, lanes_per_traj=lanes))
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("batch_steps", [7, 64, 100000])
+def test_step_batches_equal_one_shot(batch_steps):
+    T = rp.Topology.from_inputs(inputs.erdos_renyi(10, 25, 1002))
+    lanes = T.auto_lanes()
+    epl, gpl = T.shape(lanes)
+    params = rp.sample_params(T, 2002, 300, 10).to_device()
+    ref = _direct(T, params, lanes)
+    srv = rp.StepServer(rp.Opts(precision=rp.FP32), lanes, epl, gpl, max_requests=16,
+                        batch_steps=batch_steps)
+    out = rp.alloc_result(3000, T.n_genes, rp.FP32)
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    srv.submit(T, params, out, stream=stream)
+    counts = np.zeros(1, np.int32)
+    batches = 0
+    while True:
+        srv.step(stream=stream)
+        batches += 1
+        srv.done_counts(0, 1, counts, stream=stream)
+        torch.cuda.synchronize()
+        if counts[0] >= 3000:
+            break
+        assert batches < 100000
+    say(f"batch_steps={batch_steps}: {batches} step batches")
+    assert counts[0] == 3000
+    assert torch.equal(out.x, ref.x)
+    assert torch.equal(out.n_acc, ref.n_acc) and torch.equal(out.n_rej, ref.n_rej)
+    assert torch.equal(out.status, ref.status) and torch.equal(out.t_final, ref.t_final)
+
+
+def test_requests_joining_mid_flight_match_alone():
+    # Several networks of one kernel class; later ones arrive while earlier
+    # ones are parked mid-trajectory.
+    topos = [inputs.erdos_renyi(10, 25, s) for s in (1002, 3, 4, 5)]
+    Ts = [rp.Topology.from_inputs(t) for t in topos]
+    lanes = 4
+    shapes = {T.shape(lanes) for T in Ts}
+    epl = max(s[0] for s in shapes)
+    gpl = max(s[1] for s in shapes)
+    Ts = [T for T in Ts if T.shape(lanes) == (epl, gpl)]
+    assert len(Ts) >= 2
+    srv = rp.StepServer(rp.Opts(precision=rp.FP32), lanes, epl, gpl, max_requests=16, batch_steps=32)
+    stream = torch.cuda.Stream()
+    jobs = []
+    counts = np.zeros(len(Ts), np.int32)
+    for i, T in enumerate(Ts):
+        prm = rp.sample_params(T, 40 + i, 200 + 50 * i, 5).to_device()
+        out = rp.alloc_result(prm.n_sets * 5, T.n_genes, rp.FP32)
+        torch.cuda.synchronize()
+        srv.submit(T, prm, out, stream=stream)
+        jobs.append((T, prm, out))
+        for _ in range(3):  # the next request arrives while this one runs
+            srv.step(stream=stream)
+    for _ in range(100000):
+        srv.done_counts(0, len(jobs), counts, stream=stream)
+        torch.cuda.synchronize()
+        if all(counts[i] >= jobs[i][1].n_sets * 5 for i in range(len(jobs))):
+            break
+        srv.step(stream=stream)
+    for T, prm, out in jobs:
+        if T.shape(lanes) == (epl, gpl):
+            ref = _direct(T, prm, lanes)
+            assert torch.equal(out.x, ref.x)
+            assert torch.equal(out.n_acc, ref.n_acc)
+
+
+def test_scheduler_on_gpu_poisson_stream():
+    rng = np.random.default_rng(7)
+    reqs = poisson_requests(rng, 40, rate=400.0, n_lo=2, n_hi=30, p_lo=50, p_hi=3000)
+    ex = GpuExecutor(batch_steps=128)
+    sched = Scheduler(ex, hbm_budget=8 << 30)
+    done = sched.run(reqs, max_seconds=120)
+    assert len(done) == 40
+    st = sched.stats()
+    say("serving:", st)
+    # Each request equals its own one-shot solve at the same lane count.
+    for req in done[:10]:
+        T = req.handle["T"]
+        lanes = req.handle["class"][0]
+        prm = rp.sample_params(T, req.seed, req.n_sets, req.n_ic).to_device()
+        ref = _direct(T, prm, lanes)
+        assert torch.equal(req.result.x, ref.x), req.rid
+    # ... and agrees with the oracle on a few trajectories.
+    req = done[0]
+    net = oracle.canonicalize(req.topo.n_genes, req.topo.src, req.topo.dst, req.topo.sign)
+    op = oracle.sample(net, req.seed, req.n_sets, req.n_ic)
+    ids = np.arange(min(20, req.n_traj))
+    ref = oracle.steady_states(net, op, oracle.Opts(ss_rtol=1e-5), traj_ids=ids, n_threads=8)
+    gk = (op.G / op.k).T.astype(np.float64)[ids // req.n_ic]
+    err = np.abs(req.result.x.cpu().numpy()[ids] - ref.x) / gk
+    assert np.sum(err.max(axis=1) > 1e-4) <= 1
