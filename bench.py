@@ -1,16 +1,22 @@
 """RACIPE ensemble benchmark on one MI355X.
 
-Workload (one "step"): steady states of every trajectory of a seeded random
-10-gene / 25-edge signed network (Erdos-Renyi, half inhibitory, no isolated
-node), 10,000 parameter sets x 100 initial conditions = 10^6 trajectories,
-parameters from the Table 1 ranges (GRiNS Sec. 2.1.2), rtol 1e-6, atol 1e-9,
-t_end 200, steady when |dx_i/dt| <= 1e-6 + 1e-5 k_i |x_i|.  Parameters and
-initial conditions are resident in HBM before timing starts.
+Default workload (one "step"): steady states of every trajectory of a seeded
+random 10-gene / 25-edge signed network (Erdos-Renyi, half inhibitory, no
+isolated node), 10,000 parameter sets x 100 initial conditions = 10^6
+trajectories, Table 1 parameter ranges (GRiNS Sec. 2.1.2), DP5(4) with rtol
+1e-6, atol 1e-9, t_end 200, steady when |dx_i/dt| <= 1e-6 + 1e-5 k_i |x_i|.
+Parameters and initial conditions are resident in HBM before timing starts.
 
-Reported: solves/s of the chosen form (FP32 state, FP64 time / error norm /
-steady test, persistent work-queue kernel), the plain FP64 form on the same
-workload, the kernel's credited FP32 FLOP/s against the MI355X vector peak,
-and the CPU oracle timed on a bounded sample on this host.
+The JSON line reports solves/s of the chosen form (FP32 state, FP64 time /
+error norm / steady test, persistent work-queue kernel), the plain FP64 form
+on the same workload, the kernel's credited FP32 FLOP/s against the MI355X
+vector peak, p50/p99 request latency of a short Poisson serving run, and the
+CPU oracle timed on a bounded sample on this host.
+
+Other workloads (--workload): ts (2-gene toggle switch, 1000 x 10, FP64 plain
+vs FP32), uneven64 (64 networks of 5-50 genes fused in persistent launches),
+core22ts (22-gene / 82-edge network, 10^5 x 10, 101 outputs on [0, 100]),
+serve (Poisson stream, 200 req/s, 2,000 requests after 200 warm-up).
 """
 from __future__ import annotations
 
@@ -26,7 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "RACIPE ODE solves/s to steady state, batched FP32 vs plain FP64; p50/p99 latency"
-PEAK_FP32 = 157.3e12   # MI355X FP32 vector, TFLOP/s (packed)
+PEAK_FP32 = 157.3e12   # MI355X FP32 vector (published)
 PEAK_HBM = 8.0e12
 
 
@@ -54,32 +60,70 @@ def measured_traffic(workload: str):
     return None
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n-sets", type=int, default=10000)
-    ap.add_argument("--n-ic", type=int, default=100)
-    ap.add_argument("--lanes", type=int, default=0)
-    ap.add_argument("--refill-min", type=int, default=0)
-    ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle trajectories (0 = auto)")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first run a plain 1 GiB device copy, whose FETCH_SIZE/WRITE_SIZE "
-                         "counters scale the kernel's HBM traffic figures")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(trajectories are independent; see the sharding note in the design notes)",
-              file=sys.stderr)
-        sys.exit(2)
+def timed(fn, steps, stream, torch):
+    """Run fn() `steps` times between synchronisations; HIP events on the
+    launch stream bracket each call."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    return wall, np.array([e0.elapsed_time(e1) for e0, e1 in evs])
 
-    import torch
-    from paper_2503_18356_amd import inputs, flops
-    from paper_2503_18356_amd import racipe as rp
 
+def solved(rp, status) -> int:
+    st = status.cpu().numpy()
+    return int(np.isin(st, (rp.CONVERGED, rp.T_END)).sum())
+
+
+def cpu_oracle(topo, seed, n_sets, n_ic, n_sample, opts_kw=None, t_out=None):
+    import oracle
+    net = oracle.canonicalize(topo.n_genes, topo.src, topo.dst, topo.sign)
+    op = oracle.sample(net, seed, n_sets, n_ic)
+    threads = min(os.cpu_count() or 1, 16)
+    n_traj = n_sets * n_ic
+    ids = np.sort(np.random.default_rng(0).choice(n_traj, min(n_sample, n_traj), replace=False))
+    o = oracle.Opts(**(opts_kw or {"ss_rtol": 1e-5}))
+    c0 = time.perf_counter()
+    if t_out is None:
+        oracle.steady_states(net, op, o, traj_ids=ids, n_threads=threads)
+    else:
+        oracle.time_series(net, op, t_out, o, traj_ids=ids, n_threads=threads)
+    cw = time.perf_counter() - c0
+    return {"value": ids.size / cw, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"{ids.size} seeded random trajectories of the same workload, FP64 DP5(4), "
+                      f"{threads} threads, {cw:.1f} s wall"}
+
+
+def serving_run(n_req, warm, rate, seed=5, budget=64 << 30, batch_steps=256):
+    from paper_2503_18356_amd.serve import GpuExecutor, Scheduler, poisson_requests
+    rng = np.random.default_rng(seed)
+    reqs = poisson_requests(rng, n_req + warm, rate=rate)
+    ex = GpuExecutor(batch_steps=batch_steps, keep_results=False)
+    sched = Scheduler(ex, hbm_budget=budget)
+    t0 = time.perf_counter()
+    sched.run(reqs, max_seconds=900)
+    st = sched.stats(skip=warm)
+    st.update({"offered_req_per_s": rate, "warmup_requests": warm, "wall_s": time.perf_counter() - t0,
+               "kernel_classes": len(ex.classes), "batch_steps": batch_steps,
+               "what": "Poisson arrivals of random networks (N log-uniform 2-100, E = 2.5N, "
+                       "P log-uniform 1e2-1e5, n_ic U{1..10}); latency = arrival to last "
+                       "trajectory done; continuous batching in hipGraph step batches"})
+    return st
+
+
+def base_record(args):
+    return {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic"}
+
+
+def bench_er10(args, torch, rp, flops, inputs):
     dev = torch.device("cuda:0")
     if args.calibrate_copy:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -97,103 +141,218 @@ def main():
     opts = rp.Opts(precision=rp.FP32, lanes_per_traj=args.lanes, refill_min=args.refill_min)
     out = rp.alloc_result(n_traj, T.n_genes, rp.FP32, device=dev)
     stream = torch.cuda.current_stream()
-
-    def step(o, res):
-        rp.steady_states(T, dp, o, out=res, stream=stream)
-
+    step = lambda: rp.steady_states(T, dp, opts, out=out, stream=stream)
     for _ in range(args.warmup):
-        step(opts, out)
-    torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    for e0, e1 in evs:
-        e0.record(stream)
-        step(opts, out)
-        e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    lat = np.array([e0.elapsed_time(e1) for e0, e1 in evs])  # ms per launch
-    st = out.status.cpu().numpy()
+        step()
+    wall, lat = timed(step, args.steps, stream, torch)
     nacc = out.n_acc.cpu().numpy().astype(np.int64)
     nrej = out.n_rej.cpu().numpy().astype(np.int64)
-    solved = int(np.isin(st, (rp.CONVERGED, rp.T_END)).sum())
-    value = solved * args.steps / wall
-    fl = flops.credited(T.n_genes, hp.n, args.n_ic, nacc + nrej)
-    achieved = fl / (lat.mean() * 1e-3)
-    bytes_per_launch = flops.algorithmic_bytes(T.n_genes, T.n_edges, args.n_sets, args.n_ic, 4)
-
-    rec = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
+    value = solved(rp, out.status) * args.steps / wall
+    achieved = flops.credited(T.n_genes, hp.n, args.n_ic, nacc + nrej) / (lat.mean() * 1e-3)
+    nbytes = flops.algorithmic_bytes(T.n_genes, T.n_edges, args.n_sets, args.n_ic, 4)
+    default_cfg = (args.n_sets, args.n_ic, args.lanes, args.refill_min) == (10000, 100, 0, 0)
+    st = out.status.cpu().numpy()
+    rec = base_record(args)
+    rec.update({
+        "value": value, "unit": "solves/s", "ms_per_step": wall / args.steps * 1e3,
         "config": {
             "workload": "steady states, random 10-gene/25-edge signed network (ER, 50% inhibitory), "
                         "10000 parameter sets x 100 initial conditions = 1e6 trajectories, Table 1 "
                         "ranges, DP5(4) rtol 1e-6 atol 1e-9 t_end 200",
             "n_genes": T.n_genes, "n_edges": T.n_edges, "n_sets": args.n_sets, "n_ic": args.n_ic,
             "lanes_per_traj": args.lanes or T.auto_lanes(rp.FP32),
-            "precision": "FP32 state/RHS, FP64 t, error norm, steady test",
-        },
+            "precision": "FP32 state/RHS, FP64 t, error norm, steady test"},
         "roofline": {
-            "bound": "alu",
-            "achieved": achieved / 1e12,
-            "peak": PEAK_FP32 / 1e12,
-            "unit": "TFLOP/s",
+            "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32,
-            "traffic": measured_traffic("er10_1e6_fp32") if (args.n_sets, args.n_ic, args.lanes) == (10000, 100, 0) else None,
+            "traffic": measured_traffic("er10_1e6_fp32") if default_cfg else None,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "algorithmic_bytes_per_launch": bytes_per_launch,
-            "hbm_frac": bytes_per_launch / (lat.mean() * 1e-3) / PEAK_HBM,
-        },
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "what": "one full-ensemble call, enqueue to completion"},
+            "algorithmic_bytes_per_launch": nbytes,
+            "hbm_frac": nbytes / (lat.mean() * 1e-3) / PEAK_HBM},
+        "kernel_ms": {"mean": float(lat.mean()), "p50": float(np.percentile(lat, 50)),
+                      "p99": float(np.percentile(lat, 99))},
         "status_counts": {rp.STATUS_NAMES[i]: int(c) for i, c in enumerate(np.bincount(st, minlength=5))},
         "steps_per_solve": float((nacc + nrej).mean()),
         "host_sampling_s": t_sample,
-    }
-
+    })
     if not args.no_plain:
-        o64 = rp.Opts(precision=rp.FP64, ss_rtol=1e-5)
+        o64 = rp.Opts(precision=rp.FP64, ss_rtol=1e-5, lanes_per_traj=args.lanes)
         out64 = rp.alloc_result(n_traj, T.n_genes, rp.FP64, device=dev)
-        step(o64, out64)
-        torch.cuda.synchronize()
-        w0 = time.perf_counter()
-        step(o64, out64)
-        torch.cuda.synchronize()
-        w64 = time.perf_counter() - w0
-        st64 = out64.status.cpu().numpy()
-        s64 = int(np.isin(st64, (rp.CONVERGED, rp.T_END)).sum())
-        rec["plain_fp64"] = {"value": s64 / w64, "unit": "solves/s", "ms_per_step": w64 * 1e3,
+        s64 = lambda: rp.steady_states(T, dp, o64, out=out64, stream=stream)
+        s64()
+        w64, _ = timed(s64, 1, stream, torch)
+        v64 = solved(rp, out64.status) / w64
+        rec["plain_fp64"] = {"value": v64, "unit": "solves/s", "ms_per_step": w64 * 1e3,
                              "what": "FP64 state and RHS, same kernel family, same steady criterion",
                              "steps_per_solve": float((out64.n_acc.cpu().numpy().astype(np.int64)
                                                        + out64.n_rej.cpu().numpy()).mean())}
-        rec["speedup_fp32_vs_fp64"] = value / (s64 / w64)
-
+        rec["speedup_fp32_vs_fp64"] = value / v64
+        del out64
+    if not args.no_serve:
+        rec["serving"] = serving_run(args.serve_requests, args.serve_warmup, args.serve_rate)
+        rec["latency_ms"] = {"p50": rec["serving"]["p50_ms"], "p99": rec["serving"]["p99_ms"],
+                             "what": "serving request latency at the stated offered rate"}
     if not args.no_cpu:
-        import oracle
-        net = oracle.canonicalize(topo.n_genes, topo.src, topo.dst, topo.sign)
-        op = oracle.sample(net, 2002, args.n_sets, args.n_ic)
-        threads = min(os.cpu_count() or 1, 16)
-        n_cpu = args.cpu_sample or 40000
-        ids = np.sort(np.random.default_rng(0).choice(n_traj, min(n_cpu, n_traj), replace=False))
-        c0 = time.perf_counter()
-        ref = oracle.steady_states(net, op, oracle.Opts(ss_rtol=1e-5), traj_ids=ids, n_threads=threads)
-        cw = time.perf_counter() - c0
-        rec["cpu_baseline"] = {"value": ids.size / cw, "unit": "solves/s", "cores": threads,
-                               "kind": "oracle",
-                               "sample": f"{ids.size} seeded random trajectories of the same "
-                                         f"workload, FP64 DP5(4), {cw:.1f} s wall"}
+        rec["cpu_baseline"] = cpu_oracle(topo, 2002, args.n_sets, args.n_ic, args.cpu_sample or 40000)
+    return rec
+
+
+def bench_ts(args, torch, rp, flops, inputs):
+    topo = inputs.toggle_switch()
+    T = rp.Topology.from_inputs(topo)
+    hp = rp.sample_params(T, 2001, 1000, 10)
+    dp = hp.to_device()
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, o in (("fp64_plain", rp.Opts(precision=rp.FP64)), ("fp32", rp.Opts(precision=rp.FP32))):
+        out = rp.alloc_result(10000, 2, o.precision)
+        fn = lambda: rp.steady_states(T, dp, o, out=out, stream=stream)
+        fn()
+        wall, lat = timed(fn, args.steps, stream, torch)
+        res[name] = {"solves_per_s": solved(rp, out.status) * args.steps / wall,
+                     "kernel_ms": float(lat.mean())}
+    rec = base_record(args)
+    rec.update({"value": res["fp32"]["solves_per_s"], "unit": "solves/s",
+                "ms_per_step": res["fp32"]["kernel_ms"],
+                "config": {"workload": "toggle switch (A -| B, B -| A), 1000 sets x 10 ICs, "
+                                       "FP64 plain (steady |f| < 1e-6) and FP32"},
+                "forms": res})
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_oracle(topo, 2001, 1000, 10, 10000, {"ss_rtol": 0.0})
+    return rec
+
+
+def bench_uneven64(args, torch, rp, flops, inputs):
+    rng = np.random.default_rng(1003)
+    topos = inputs.uneven_batch(1003, n_networks=64, n_min=5, n_max=50)
+    Ts = [rp.Topology.from_inputs(t) for t in topos]
+    Ps = [inputs.log_uniform_int(rng, 2000, 50000) for _ in topos]
+    items = []
+    for i, (T, P) in enumerate(zip(Ts, Ps)):
+        items.append((T, rp.sample_params(T, 3000 + i, P, 10).to_device()))
+    n_traj = sum(P * 10 for P in Ps)
+    stream = torch.cuda.current_stream()
+    o32 = rp.Opts(precision=rp.FP32)
+    outs = [rp.alloc_result(p.n_sets * 10, T.n_genes, rp.FP32) for T, p in items]
+    fn = lambda: rp.steady_states_batch([(T, p, o) for (T, p), o in zip(items, outs)], o32, stream=stream)
+    fn()
+    wall, lat = timed(fn, args.steps, stream, torch)
+    v32 = sum(solved(rp, o.status) for o in outs) * args.steps / wall
+    fl = sum(flops.credited(T.n_genes, p.n.cpu().numpy(), 10,
+                            (o.n_acc.cpu().numpy().astype(np.int64) + o.n_rej.cpu().numpy()))
+             for (T, p), o in zip(items, outs))
+    o64 = rp.Opts(precision=rp.FP64, ss_rtol=1e-5)
+    outs64 = [rp.alloc_result(p.n_sets * 10, T.n_genes, rp.FP64) for T, p in items]
+
+    def plain():
+        for (T, p), o in zip(items, outs64):
+            rp.steady_states(T, p, o64, out=o, stream=stream)
+    plain()
+    w64, _ = timed(plain, 1, stream, torch)
+    v64 = sum(solved(rp, o.status) for o in outs64) / w64
+    rec = base_record(args)
+    rec.update({"value": v32, "unit": "solves/s", "ms_per_step": wall / args.steps * 1e3,
+                "config": {"workload": "64 random signed networks, N ~ U{5..50}, E = 2.5N, half "
+                                       "inhibitory, P log-uniform 2000-50000 x 10 ICs, one "
+                                       "persistent launch per kernel shape",
+                           "trajectories": n_traj},
+                "roofline": {"bound": "alu", "achieved": fl / (lat.mean() * 1e-3) / 1e12,
+                             "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                             "frac": fl / (lat.mean() * 1e-3) / PEAK_FP32, "traffic": None},
+                "plain_fp64": {"value": v64, "unit": "solves/s",
+                               "what": "FP64, one launch per network"},
+                "speedup_fp32_vs_fp64": v32 / v64})
+    return rec
+
+
+def bench_core22ts(args, torch, rp, flops, inputs):
+    topo = inputs.dense_core(1004)
+    T = rp.Topology.from_inputs(topo)
+    P, n_ic = 100000, 10
+    hp = rp.sample_params(T, 2004, P, n_ic)
+    dp = hp.to_device()
+    tk = np.linspace(0.0, 100.0, 101)
+    stream = torch.cuda.current_stream()
+    o32 = rp.Opts(precision=rp.FP32)
+    out = rp.alloc_result(P * n_ic, T.n_genes, rp.FP32, n_t=101)
+    fn = lambda: rp.integrate(T, dp, tk, o32, out=out, stream=stream)
+    fn()
+    wall, lat = timed(fn, args.steps, stream, torch)
+    steps = out.n_acc.cpu().numpy().astype(np.int64) + out.n_rej.cpu().numpy()
+    fl = flops.credited(T.n_genes, hp.n, n_ic, steps)
+    v32 = solved(rp, out.status) * args.steps / wall
+    del out
+    o64 = rp.Opts(precision=rp.FP64)
+    out64 = rp.alloc_result(P * n_ic, T.n_genes, rp.FP64, n_t=101)
+    f64 = lambda: rp.integrate(T, dp, tk, o64, out=out64, stream=stream)
+    f64()
+    w64, _ = timed(f64, 1, stream, torch)
+    v64 = solved(rp, out64.status) / w64
+    del out64
+    nbytes = flops.algorithmic_bytes(T.n_genes, T.n_edges, P, n_ic, 4, n_t=101)
+    rec = base_record(args)
+    rec.update({"value": v32, "unit": "solves/s", "ms_per_step": wall / args.steps * 1e3,
+                "config": {"workload": "22-gene / 82-edge dense-core network (49 inhibitory), "
+                                       "1e5 sets x 10 ICs, 101 outputs on [0, 100]",
+                           "lanes_per_traj": T.auto_lanes()},
+                "roofline": {"bound": "alu", "achieved": fl / (lat.mean() * 1e-3) / 1e12,
+                             "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                             "frac": fl / (lat.mean() * 1e-3) / PEAK_FP32, "traffic": None,
+                             "algorithmic_bytes_per_launch": nbytes,
+                             "hbm_frac": nbytes / (lat.mean() * 1e-3) / PEAK_HBM},
+                "plain_fp64": {"value": v64, "unit": "solves/s"},
+                "speedup_fp32_vs_fp64": v32 / v64})
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_oracle(topo, 2004, P, n_ic, 3000, {"ss_rtol": 1e-5}, t_out=tk)
+    return rec
+
+
+def bench_serve(args, torch, rp, flops, inputs):
+    st = serving_run(args.serve_requests, args.serve_warmup, args.serve_rate)
+    rec = base_record(args)
+    rec.update({"value": st["solves_per_s"], "unit": "solves/s", "ms_per_step": None,
+                "latency_ms": {"p50": st["p50_ms"], "p99": st["p99_ms"]},
+                "config": {"workload": "serving: Poisson request stream"}, "serving": st})
+    return rec
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="er10", choices=["er10", "ts", "uneven64", "core22ts", "serve"])
+    ap.add_argument("--n-sets", type=int, default=10000)
+    ap.add_argument("--n-ic", type=int, default=100)
+    ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--refill-min", type=int, default=0)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=None)
+    ap.add_argument("--serve-warmup", type=int, default=None)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle trajectories (0 = auto)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy, whose FETCH_SIZE/WRITE_SIZE "
+                         "counters scale the kernel's HBM traffic figures")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(trajectories are independent; the sharding design is in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    if args.serve_requests is None:
+        args.serve_requests = 2000 if args.workload == "serve" else 300
+    if args.serve_warmup is None:
+        args.serve_warmup = 200 if args.workload == "serve" else 30
+
+    import torch
+    from paper_2503_18356_amd import flops, inputs
+    from paper_2503_18356_amd import racipe as rp
+
+    fn = {"er10": bench_er10, "ts": bench_ts, "uneven64": bench_uneven64,
+          "core22ts": bench_core22ts, "serve": bench_serve}[args.workload]
+    rec = fn(args, torch, rp, flops, inputs)
     print(json.dumps(rec), flush=True)
 
 

@@ -1,0 +1,31 @@
+"""Algorithmic work accounting and autotune bucketing (CPU)."""
+import numpy as np
+
+from paper_2503_18356_amd import flops, inputs
+
+
+def test_multiplication_chains():
+    # Shortest addition chains: q^1..q^6 need 0, 1, 2, 2, 3, 3 multiplies.
+    assert list(flops.CHAIN[1:7]) == [0, 1, 2, 2, 3, 3]
+
+
+def test_rhs_and_step_flops():
+    n = np.array([[1, 6], [3, 2]], np.uint8)  # 2 edges x 2 sets
+    f = flops.rhs_flops_per_set(4, n)
+    assert list(f) == [(6 + 0) + (6 + 2) + 12, (6 + 3) + (6 + 1) + 12]
+    s = flops.step_flops_per_set(4, n)
+    assert list(s) == [6 * f[0] + 56 * 4, 6 * f[1] + 56 * 4]
+    steps = np.array([10, 20, 5, 5])  # 2 sets x 2 ICs
+    assert flops.credited(4, n, 2, steps) == s[0] * 30 + s[1] * 10
+
+
+def test_algorithmic_bytes():
+    b = flops.algorithmic_bytes(10, 25, 100, 10, 4)
+    assert b == 100 * ((20 + 50) * 4 + 25) + 10 * 40 + 1000 * (40 + 17)
+
+
+def test_autotune_bucket_rounds_up():
+    from paper_2503_18356_amd.autotune import bucket
+    t = inputs.erdos_renyi(10, 25, 1002)
+    b = bucket(t)
+    assert b.startswith("N16_E32_D")
