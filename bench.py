@@ -107,7 +107,7 @@ def serving_run(n_req, warm, rate, seed=5, budget=64 << 30, batch_steps=256):
     ex = GpuExecutor(batch_steps=batch_steps, keep_results=False)
     sched = Scheduler(ex, hbm_budget=budget)
     t0 = time.perf_counter()
-    sched.run(reqs, max_seconds=900)
+    sched.run(reqs, max_seconds=900, progress=lambda m: print(m, file=sys.stderr, flush=True))
     st = sched.stats(skip=warm)
     st.update({"offered_req_per_s": rate, "warmup_requests": warm, "wall_s": time.perf_counter() - t0,
                "kernel_classes": len(ex.classes), "batch_steps": batch_steps,

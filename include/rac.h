@@ -248,7 +248,9 @@ rac_status rac_steady_states_batch(const rac_batch_item* items, int32_t n_items,
  * Ownership: the server owns its device memory (request table of
  * max_requests entries, slot table sized for one full grid); submitted
  * arrays stay caller-owned and must stay valid until the request's done
- * count reaches P * n_ic.  One server is used from one stream at a time. */
+ * count reaches P * n_ic.  One server is used from one stream at a time:
+ * submits and step batches must be ordered on it (a batch's last graph node
+ * resets a queue head that the batch left past the tail). */
 typedef struct rac_server rac_server;
 
 /* EINVAL: bad opts, lanes_per_traj < 1, max_requests < 1, batch_steps < 1.

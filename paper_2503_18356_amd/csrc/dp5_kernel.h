@@ -43,19 +43,23 @@ template <>
 struct Ops<float> {
     using NType = float;
     __device__ static float to_n(int n) { return (float)n; }
-    // Shifted Hill factor divided by sqrt(lambda):
-    //   H^S / sqrt(lam) = beta' + delta' / (1 + (x/T)^n),
+    // Sources publish log2 of their level once per evaluation and edges keep
+    // log2 T, so an edge costs one exp2 and one reciprocal:
+    //   H^S / sqrt(lam) = beta' + delta' / (1 + 2^(n (log2 x - log2 T))),
     //   beta' = sqrt(lam), delta' = 1/sqrt(lam) - sqrt(lam).
-    __device__ static float hill(float xs, float invT, float n, float b, float d) {
-        const float q = xs * invT;
-        const float r = __builtin_amdgcn_exp2f(n * __builtin_amdgcn_logf(q));
+    // x = 0 publishes -inf, giving r = 0 and H^S = 1.
+    __device__ static float publish(float v) { return __builtin_amdgcn_logf(v > 0.0f ? v : 0.0f); }
+    __device__ static float edge_t(float T) { return __builtin_amdgcn_logf(T); }
+    __device__ static float hill(float lx, float lT, float n, float b, float d) {
+        const float r = __builtin_amdgcn_exp2f(n * (lx - lT));
         return __builtin_fmaf(d, __builtin_amdgcn_rcpf(1.0f + r), b);
     }
     __device__ static float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
     __device__ static float sqrt(float v) { return __builtin_sqrtf(v); }
-    // Step factor err^(-1/5) (FP32 is ample for a controller factor).
-    __device__ static double pow_m15(double err) {
-        return (double)__builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf((float)err));
+    // Step factor err^(-1/5) from the mean square err^2 (FP32 is ample for a
+    // controller factor).
+    __device__ static double pow_m15_sq(double err2) {
+        return (double)__builtin_amdgcn_exp2f(-0.1f * __builtin_amdgcn_logf((float)err2));
     }
 };
 
@@ -63,6 +67,9 @@ template <>
 struct Ops<double> {
     using NType = int;
     __device__ static int to_n(int n) { return n; }
+    // Sources publish their level, edges keep 1/T; (x/T)^n by squaring.
+    __device__ static double publish(double v) { return v > 0.0 ? v : 0.0; }
+    __device__ static double edge_t(double T) { return 1.0 / T; }
     __device__ static double hill(double xs, double invT, int n, double b, double d) {
         const double q = xs * invT;
         double r = 1.0, base = q;
@@ -74,7 +81,7 @@ struct Ops<double> {
     }
     __device__ static double rcp(double v) { return 1.0 / v; }
     __device__ static double sqrt(double v) { return ::sqrt(v); }
-    __device__ static double pow_m15(double err) { return ::pow(err, -0.2); }
+    __device__ static double pow_m15_sq(double err2) { return ::pow(err2, -0.1); }
 };
 
 // Wave-level ordering of LDS writes before reads by other lanes of the wave.
@@ -125,8 +132,12 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
     const Controls& c = a.c;
 
     st(pre_base, (R)1);  // prefix[0] = 1, never overwritten
+    // Padding edge slots read the sink; give it a finite value so that their
+    // factor is exactly 1 even for lanes that hold no padding gene slot.
+    st(sink, (R)0);
 
-    // Edge slots: source address, 1/T, n, sqrt(lam), 1/sqrt(lam) - sqrt(lam).
+    // Edge slots: source address, threshold term (O::edge_t), n, sqrt(lam),
+    // 1/sqrt(lam) - sqrt(lam).
     uint32_t e_xa[EPL];
     R e_invT[EPL], e_b[EPL], e_d[EPL];
     NT e_n[EPL];
@@ -154,12 +165,13 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
     bool exhausted = false;
     uint64_t popped = 0;  // queue position after this wave's last pop
     int n_genes = 1;
+    double inv_n = 1.0;   // 1 / n_genes of the group's network
 
     // One right-hand-side evaluation f(yv) for every lane of the wave: no
     // branches, padding slots evaluate factors of exactly 1.
     auto rhs = [&](const R (&yv)[GPL], R (&f)[GPL]) {
 #pragma unroll
-        for (int q = 0; q < GPL; ++q) st(g_wa[q], yv[q] > (R)0 ? yv[q] : (R)0);
+        for (int q = 0; q < GPL; ++q) st(g_wa[q], O::publish(yv[q]));
         wave_sync();
         R run = 1;
 #pragma unroll
@@ -263,6 +275,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
             const int ci = (int)(local - p * n_ic);
             const int64_t P = RAC_DF(n_sets);
             n_genes = RAC_DF(n_genes);
+            inv_n = 1.0 / n_genes;
             const int stride = RAC_DF(stride);
             const int32_t* lane_edge = RAC_DF(lane_edge) + r * stride;
             const float* Tp = RAC_DF(T) + p;
@@ -277,7 +290,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
                     const R Tv = (R)Tp[e * P];
                     const R sl = O::sqrt((R)Lp[e * P]);
                     e_xa[s] = (wave_elem + (uint32_t)(src * n_groups + g)) * SZ;
-                    e_invT[s] = (R)1 / Tv;
+                    e_invT[s] = O::edge_t(Tv);
                     e_n[s] = O::to_n((int)Np[e * P]);
                     e_b[s] = sl;
                     e_d[s] = (R)1 / sl - sl;
@@ -382,31 +395,13 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
             if (nfree > 0 && (nfree >= c.refill_min || busy_lead == 0 || near_end)) {
                 unsigned long long base = 0, got = 0;
                 if (lane == 0) {
-                    if (BOUNDED) {
-                        // The host may append work between launches, so never
-                        // move head past total: claim [head, min(head + nfree, total)).
-                        unsigned long long head =
-                            __hip_atomic_load(&a.ctl->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        for (;;) {
-                            if (head >= total) {
-                                base = head;
-                                got = 0;
-                                break;
-                            }
-                            const unsigned long long want =
-                                head + (unsigned long long)nfree < total ? head + nfree : total;
-                            const unsigned long long old = atomicCAS(&a.ctl->head, head, want);
-                            if (old == head) {
-                                base = head;
-                                got = want - head;
-                                break;
-                            }
-                            head = old;
-                        }
-                    } else {
-                        base = atomicAdd(a.counter, (unsigned long long)nfree);
-                        got = (unsigned long long)nfree;
-                    }
+                    // One atomic per wave.  In step batches head may run past
+                    // total; the batch's last graph node clamps it back before
+                    // the host appends more, so appended indices are served.
+                    base = atomicAdd(a.counter, (unsigned long long)nfree);
+                    got = base >= total ? 0ull
+                                        : (base + (unsigned long long)nfree <= total ? (unsigned long long)nfree
+                                                                                    : total - base);
                 }
                 base = __shfl(base, 0);
                 got = __shfl(got, 0);
@@ -550,15 +545,20 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
             serr += rq * rq;
             fin = fin && (g_id[q] < 0 || __builtin_isfinite((double)y[q]));
         }
-        const double err = sqrt(group_sum(serr) / n_genes);
+        // Accept iff the RMS error is <= 1, i.e. its square is; one factor
+        // 0.9 err^(-1/5), clamped to [0.2, 10] after an accepted step that did
+        // not follow a rejection and to [0.2, 1] otherwise.
+        const double err2 = group_sum(serr) * inv_n;
         const bool all_fin = group_all(fin);  // collective: evaluated by every lane
-        const bool accept = running && all_fin && __builtin_isfinite(err) && err <= 1.0;
-        if (running && !accept) {
-            ++nrej;
-            double fac = __builtin_isfinite(err) ? 0.9 * O::pow_m15(err) : 0.2;
-            fac = fac < 0.2 ? 0.2 : (fac > 1.0 ? 1.0 : fac);
+        const bool accept = running && all_fin && err2 <= 1.0;
+        const bool err_ok = __builtin_isfinite(err2);
+        double fac = !err_ok ? 0.2 : (err2 > 0 ? 0.9 * O::pow_m15_sq(err2) : 10.0);
+        const double fmax = (accept && !last_rej) ? 10.0 : 1.0;
+        fac = fac < 0.2 ? 0.2 : (fac > fmax ? fmax : fac);
+        if (running) {
             h = hs * fac;
-            last_rej = true;
+            nrej += accept ? 0 : 1;
+            last_rej = !accept;
         }
         // Dense output for every output time inside the accepted step.
         if (TS && accept && kout < a.n_t && a.t_out[kout] <= (clipped ? t_stop : t + hs)) {
@@ -598,11 +598,6 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
                                     fabs((double)kk[0][q]) <=
                                         c.ss_atol + c.ss_rtol * (double)gk[q] * fabs((double)x[q]));
             }
-            double fac = err > 0 ? 0.9 * O::pow_m15(err) : 10.0;
-            const double fmax = last_rej ? 1.0 : 10.0;
-            fac = fac > fmax ? fmax : (fac < 0.2 ? 0.2 : fac);
-            h = hs * fac;
-            last_rej = false;
         }
         const bool all_steady = group_all(steady);
         if (accept) {

@@ -50,6 +50,13 @@ struct rac_server {
 namespace rac {
 namespace {
 
+// Undo a queue head that ran past the tail during a batch (claims beyond the
+// tail were never served).  Last node of every step batch, so it runs before
+// a later submit moves the tail.
+__global__ void clamp_head(ServeCtl* c) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && c->head > c->total) c->head = c->total;
+}
+
 #define RAC_SHIP(call, what)                                                            \
     do {                                                                                \
         hipError_t e_ = (call);                                                         \
@@ -212,6 +219,10 @@ rac_status rac_server_step(rac_server* s, void* hip_stream) {
         RAC_SHIP(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed), "rac_server_step: begin capture");
         void* args[] = {&s->args};
         hipError_t le = hipLaunchKernel(s->ke->fn, dim3(s->grid), dim3(kBlock), args, 0, stream);
+        if (le == hipSuccess) {
+            hipLaunchKernelGGL(clamp_head, dim3(1), dim3(64), 0, stream, s->ctl);
+            le = hipGetLastError();
+        }
         hipGraph_t g = nullptr;
         hipError_t ce = hipStreamEndCapture(stream, &g);
         if (le != hipSuccess || ce != hipSuccess)

@@ -102,13 +102,20 @@ class Scheduler:
     def idle(self) -> bool:
         return not self.waiting and not self.running
 
-    def run(self, arrivals: list[Request], until_idle: bool = True, max_seconds: float = 600.0):
-        """Feed requests at their arrival times (seconds from now) and serve."""
+    def run(self, arrivals: list[Request], until_idle: bool = True, max_seconds: float = 600.0,
+            progress=None, progress_every: float = 10.0):
+        """Feed requests at their arrival times (seconds from now) and serve.
+        ``progress(msg)`` is called every ``progress_every`` seconds."""
         pending = sorted(arrivals, key=lambda r: r.arrival)
         i = 0
         self.t0 = self.clock()
+        next_report = progress_every
         while True:
             now = self.now()
+            if progress is not None and now >= next_report:
+                next_report = now + progress_every
+                progress(f"serve t={now:.1f}s arrived={i}/{len(pending)} waiting={len(self.waiting)} "
+                         f"running={len(self.running)} done={len(self.done)}")
             while i < len(pending) and pending[i].arrival <= now:
                 self.arrive(pending[i])
                 i += 1
@@ -140,10 +147,18 @@ class Scheduler:
 
 class GpuExecutor:
     """Runs admitted requests on the GPU through rac_server step batches, one
-    server (and stream) per kernel class (lanes per trajectory, slot shape)."""
+    server per kernel class (lanes per trajectory, slot shape).
+
+    A network joins an existing class of its lane count whose shape is at
+    least its own when that costs at most ``merge_slack`` times the per-step
+    work of its own shape (padding slots compute factors of exactly one), so
+    a mix of networks runs in few classes.  Classes share a small pool of
+    streams; each loop iteration enqueues one batch per active class and the
+    finished counts of all classes, then waits once."""
 
     def __init__(self, opts=None, batch_steps: int = 256, max_requests: int = 65536,
-                 device="cuda", keep_results: bool = True):
+                 device="cuda", keep_results: bool = True, merge_slack: float = 1.5,
+                 n_streams: int = 4):
         import torch
         from . import racipe as rp
         self.rp = rp
@@ -153,17 +168,33 @@ class GpuExecutor:
         self.max_requests = max_requests
         self.device = device
         self.keep_results = keep_results
+        self.merge_slack = merge_slack
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(max(1, n_streams))]
         self.classes: dict[tuple, dict] = {}
-        self.topo_cache: dict[int, object] = {}
+
+    @staticmethod
+    def slot_cost(epl: int, gpl: int) -> float:
+        # Per-step issue cost model of a kernel shape (edge and gene slots).
+        return 14.0 * epl + 25.0 * gpl + 40.0
 
     def _class(self, T):
         lanes = T.auto_lanes(self.rp.FP32)
         epl, gpl = T.shape(lanes, self.rp.FP32)
+        own = self.slot_cost(epl, gpl)
+        best = None
+        for key, cl in self.classes.items():
+            kl, ke, kg = key
+            if kl == lanes and ke >= epl and kg >= gpl:
+                c = self.slot_cost(ke, kg)
+                if c <= self.merge_slack * own and (best is None or c < best[0]):
+                    best = (c, key)
+        if best is not None:
+            return best[1], self.classes[best[1]]
         key = (lanes, epl, gpl)
-        if key not in self.classes:
-            srv = self.rp.StepServer(self.opts, lanes, epl, gpl, self.max_requests, self.batch_steps)
-            self.classes[key] = {"server": srv, "stream": self.torch.cuda.Stream(device=self.device),
-                                 "active": {}, "counts": np.zeros(self.max_requests, np.int32)}
+        srv = self.rp.StepServer(self.opts, lanes, epl, gpl, self.max_requests, self.batch_steps)
+        counts = self.torch.zeros(self.max_requests, dtype=self.torch.int32, pin_memory=True)
+        self.classes[key] = {"server": srv, "stream": self.streams[len(self.classes) % len(self.streams)],
+                             "active": {}, "counts_t": counts, "counts": counts.numpy()}
         return key, self.classes[key]
 
     def start(self, req: Request):
@@ -186,14 +217,18 @@ class GpuExecutor:
                 cl["server"].step(stream=cl["stream"])
 
     def finished(self) -> list[int]:
-        out = []
+        polled = []
         for cl in self.classes.values():
             act = cl["active"]
-            if not act:
-                continue
-            lo, hi = min(act), max(act) + 1
-            cl["server"].done_counts(lo, hi - lo, cl["counts"], stream=cl["stream"])
-            cl["stream"].synchronize()
+            if act:
+                lo, hi = min(act), max(act) + 1
+                cl["server"].done_counts(lo, hi - lo, cl["counts"], stream=cl["stream"])
+                polled.append((cl, lo))
+        for st in {id(cl["stream"]): cl["stream"] for cl, _ in polled}.values():
+            st.synchronize()
+        out = []
+        for cl, lo in polled:
+            act = cl["active"]
             for srv_rid in list(act):
                 req = act[srv_rid]
                 if cl["counts"][srv_rid - lo] >= req.n_traj:

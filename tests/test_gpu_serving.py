@@ -106,17 +106,82 @@ def test_requests_joining_mid_flight_match_alone():
         jobs.append((T, prm, out))
         for _ in range(3):  # the next request arrives while this one runs
             srv.step(stream=stream)
-    for _ in range(100000):
+    for _ in range(20000):
         srv.done_counts(0, len(jobs), counts, stream=stream)
         torch.cuda.synchronize()
         if all(counts[i] >= jobs[i][1].n_sets * 5 for i in range(len(jobs))):
             break
         srv.step(stream=stream)
+    else:
+        pytest.fail(f"requests did not finish: done {counts.tolist()}")
     for T, prm, out in jobs:
         if T.shape(lanes) == (epl, gpl):
             ref = _direct(T, prm, lanes)
             assert torch.equal(out.x, ref.x)
             assert torch.equal(out.n_acc, ref.n_acc)
+
+
+def test_request_after_drained_queue_is_served():
+    # The first request is fully claimed in its first batch, so the queue
+    # head runs past the tail; a request appended afterwards must still run.
+    T = rp.Topology.from_inputs(inputs.toggle_switch())
+    lanes = T.auto_lanes()
+    epl, gpl = T.shape(lanes)
+    srv = rp.StepServer(rp.Opts(precision=rp.FP32), lanes, epl, gpl, max_requests=8, batch_steps=16)
+    stream = torch.cuda.Stream()
+    jobs = []
+    counts = np.zeros(3, np.int32)
+    for i, P in enumerate((30, 5, 64)):
+        prm = rp.sample_params(T, 70 + i, P, 2).to_device()
+        out = rp.alloc_result(P * 2, T.n_genes, rp.FP32)
+        torch.cuda.synchronize()
+        srv.submit(T, prm, out, stream=stream)
+        jobs.append((prm, out))
+        for _ in range(50):
+            srv.step(stream=stream)
+    for _ in range(5000):
+        srv.done_counts(0, 3, counts, stream=stream)
+        torch.cuda.synchronize()
+        if all(counts[i] >= jobs[i][0].n_sets * 2 for i in range(3)):
+            break
+        srv.step(stream=stream)
+    else:
+        pytest.fail(f"requests did not finish: done {counts.tolist()}")
+    for prm, out in jobs:
+        ref = _direct(T, prm, lanes)
+        assert torch.equal(out.x, ref.x) and torch.equal(out.n_acc, ref.n_acc)
+
+
+def test_network_in_a_larger_shape_matches_its_own():
+    # A server of a larger kernel shape pads the network's slots with factors
+    # of exactly one: results are bit-identical to the network's own shape.
+    T = rp.Topology.from_inputs(inputs.erdos_renyi(10, 25, 1002))
+    lanes = T.auto_lanes()
+    epl, gpl = T.shape(lanes)
+    big = (min(e for e in (4, 8, 12, 16, 24, 32) if e > epl), min(g for g in (1, 2, 3, 4, 6, 8) if g > gpl))
+    params = rp.sample_params(T, 91, 400, 3).to_device()
+    ref = _direct(T, params, lanes)
+    try:
+        srv = rp.StepServer(rp.Opts(precision=rp.FP32), lanes, big[0], big[1], max_requests=4,
+                            batch_steps=40)
+    except rp.RacError:
+        pytest.skip(f"no compiled serving shape {big}")
+    say(f"own shape {(epl, gpl)}, server shape {big}, lanes {lanes}")
+    out = rp.alloc_result(1200, T.n_genes, rp.FP32)
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    srv.submit(T, params, out, stream=stream)
+    counts = np.zeros(1, np.int32)
+    for _ in range(5000):
+        srv.step(stream=stream)
+        srv.done_counts(0, 1, counts, stream=stream)
+        torch.cuda.synchronize()
+        if counts[0] >= 1200:
+            break
+    else:
+        pytest.fail("request did not finish")
+    assert torch.equal(out.x, ref.x)
+    assert torch.equal(out.n_acc, ref.n_acc) and torch.equal(out.status, ref.status)
 
 
 def test_scheduler_on_gpu_poisson_stream():
