@@ -81,23 +81,63 @@ def solved(rp, status) -> int:
     return int(np.isin(st, (rp.CONVERGED, rp.T_END)).sum())
 
 
-def cpu_oracle(topo, seed, n_sets, n_ic, n_sample, opts_kw=None, t_out=None):
+def cpu_oracle(topo, seed, n_sets, n_ic, n_pilot, opts_kw=None, t_out=None, target_s=12.0):
+    """The FP64 oracle on the host's cores over a seeded random sample of the
+    workload's trajectories: a pilot of n_pilot trajectories sizes the timed
+    sample to about target_s seconds (capped at the whole workload)."""
     import oracle
     net = oracle.canonicalize(topo.n_genes, topo.src, topo.dst, topo.sign)
     op = oracle.sample(net, seed, n_sets, n_ic)
     threads = min(os.cpu_count() or 1, 16)
     n_traj = n_sets * n_ic
-    ids = np.sort(np.random.default_rng(0).choice(n_traj, min(n_sample, n_traj), replace=False))
     o = oracle.Opts(**(opts_kw or {"ss_rtol": 1e-5}))
-    c0 = time.perf_counter()
-    if t_out is None:
-        oracle.steady_states(net, op, o, traj_ids=ids, n_threads=threads)
-    else:
-        oracle.time_series(net, op, t_out, o, traj_ids=ids, n_threads=threads)
-    cw = time.perf_counter() - c0
-    return {"value": ids.size / cw, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"{ids.size} seeded random trajectories of the same workload, FP64 DP5(4), "
-                      f"{threads} threads, {cw:.1f} s wall"}
+    rng = np.random.default_rng(0)
+
+    def run(n):
+        ids = np.sort(rng.choice(n_traj, min(n, n_traj), replace=False))
+        c0 = time.perf_counter()
+        if t_out is None:
+            oracle.steady_states(net, op, o, traj_ids=ids, n_threads=threads)
+        else:
+            oracle.time_series(net, op, t_out, o, traj_ids=ids, n_threads=threads)
+        return ids.size, time.perf_counter() - c0
+
+    n0, w0 = run(n_pilot)
+    n1, cw = run(max(n_pilot, int(n0 / max(w0, 1e-3) * target_s)))
+    return {"value": n1 / cw, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n1} seeded random trajectories of the same workload (sized by a "
+                      f"{n0}-trajectory pilot), FP64 DP5(4), {threads} threads, {cw:.1f} s wall"}
+
+
+def cpu_oracle_multi(nets, n_pilot, target_s=12.0):
+    """cpu_oracle over several networks: nets = [(topo, seed, n_sets, n_ic)];
+    the sample draws trajectories across networks in proportion to their
+    counts."""
+    import oracle
+    threads = min(os.cpu_count() or 1, 16)
+    prepared = []
+    for topo, seed, P, n_ic in nets:
+        net = oracle.canonicalize(topo.n_genes, topo.src, topo.dst, topo.sign)
+        prepared.append((net, oracle.sample(net, seed, P, n_ic), P * n_ic))
+    sizes = np.array([n for _, _, n in prepared], dtype=np.int64)
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    o = oracle.Opts(ss_rtol=1e-5)
+    rng = np.random.default_rng(0)
+
+    def run(n):
+        ids = np.sort(rng.choice(int(starts[-1]), min(n, int(starts[-1])), replace=False))
+        c0 = time.perf_counter()
+        for i, (net, op, _) in enumerate(prepared):
+            sel = ids[(ids >= starts[i]) & (ids < starts[i + 1])] - starts[i]
+            if sel.size:
+                oracle.steady_states(net, op, o, traj_ids=sel, n_threads=threads)
+        return ids.size, time.perf_counter() - c0
+
+    n0, w0 = run(n_pilot)
+    n1, cw = run(max(n_pilot, int(n0 / max(w0, 1e-3) * target_s)))
+    return {"value": n1 / cw, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n1} seeded random trajectories across the workload's networks (sized by "
+                      f"a {n0}-trajectory pilot), FP64 DP5(4), {threads} threads, {cw:.1f} s wall"}
 
 
 def serving_run(n_req, warm, rate, seed=5, budget=64 << 30, batch_steps=256):
@@ -193,7 +233,7 @@ def bench_er10(args, torch, rp, flops, inputs):
         rec["latency_ms"] = {"p50": rec["serving"]["p50_ms"], "p99": rec["serving"]["p99_ms"],
                              "what": "serving request latency at the stated offered rate"}
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_oracle(topo, 2002, args.n_sets, args.n_ic, args.cpu_sample or 40000)
+        rec["cpu_baseline"] = cpu_oracle(topo, 2002, args.n_sets, args.n_ic, args.cpu_sample or 20000)
     return rec
 
 
@@ -218,7 +258,7 @@ def bench_ts(args, torch, rp, flops, inputs):
                                        "FP64 plain (steady |f| < 1e-6) and FP32"},
                 "forms": res})
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_oracle(topo, 2001, 1000, 10, 10000, {"ss_rtol": 0.0})
+        rec["cpu_baseline"] = cpu_oracle(topo, 2001, 1000, 10, 2000, {"ss_rtol": 0.0})
     return rec
 
 
@@ -262,6 +302,9 @@ def bench_uneven64(args, torch, rp, flops, inputs):
                 "plain_fp64": {"value": v64, "unit": "solves/s",
                                "what": "FP64, one launch per network"},
                 "speedup_fp32_vs_fp64": v32 / v64})
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_oracle_multi(
+            [(t, 3000 + i, P, 10) for i, (t, P) in enumerate(zip(topos, Ps))], 4000)
     return rec
 
 
@@ -303,7 +346,7 @@ def bench_core22ts(args, torch, rp, flops, inputs):
                 "plain_fp64": {"value": v64, "unit": "solves/s"},
                 "speedup_fp32_vs_fp64": v32 / v64})
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_oracle(topo, 2004, P, n_ic, 3000, {"ss_rtol": 1e-5}, t_out=tk)
+        rec["cpu_baseline"] = cpu_oracle(topo, 2004, P, n_ic, 1000, {"ss_rtol": 1e-5}, t_out=tk)
     return rec
 
 

@@ -44,17 +44,18 @@ struct Ops<float> {
     using NType = float;
     __device__ static float to_n(int n) { return (float)n; }
     // Sources publish log2 of their level once per evaluation and edges keep
-    // log2 T, so an edge costs one exp2 and one reciprocal:
-    //   H^S / sqrt(lam) = beta' + delta' / (1 + 2^(n (log2 x - log2 T))),
+    // n log2 T, so an edge costs one fma, one exp2 and one reciprocal:
+    //   H^S / sqrt(lam) = beta' + delta' / (1 + 2^(n log2 x - n log2 T)),
     //   beta' = sqrt(lam), delta' = 1/sqrt(lam) - sqrt(lam).
     // x = 0 publishes -inf, giving r = 0 and H^S = 1.
     __device__ static float publish(float v) { return __builtin_amdgcn_logf(v > 0.0f ? v : 0.0f); }
-    __device__ static float edge_t(float T) { return __builtin_amdgcn_logf(T); }
-    __device__ static float hill(float lx, float lT, float n, float b, float d) {
-        const float r = __builtin_amdgcn_exp2f(n * (lx - lT));
+    __device__ static float edge_t(float T, int n) { return (float)n * __builtin_amdgcn_logf(T); }
+    __device__ static float hill(float lx, float nlT, float n, float b, float d) {
+        const float r = __builtin_amdgcn_exp2f(__builtin_fmaf(n, lx, -nlT));
         return __builtin_fmaf(d, __builtin_amdgcn_rcpf(1.0f + r), b);
     }
     __device__ static float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
+    __device__ static float abs(float v) { return __builtin_fabsf(v); }
     __device__ static float sqrt(float v) { return __builtin_sqrtf(v); }
     // Step factor err^(-1/5) from the mean square err^2 (FP32 is ample for a
     // controller factor).
@@ -69,7 +70,7 @@ struct Ops<double> {
     __device__ static int to_n(int n) { return n; }
     // Sources publish their level, edges keep 1/T; (x/T)^n by squaring.
     __device__ static double publish(double v) { return v > 0.0 ? v : 0.0; }
-    __device__ static double edge_t(double T) { return 1.0 / T; }
+    __device__ static double edge_t(double T, int) { return 1.0 / T; }
     __device__ static double hill(double xs, double invT, int n, double b, double d) {
         const double q = xs * invT;
         double r = 1.0, base = q;
@@ -80,6 +81,7 @@ struct Ops<double> {
         return fma(d, 1.0 / (1.0 + r), b);
     }
     __device__ static double rcp(double v) { return 1.0 / v; }
+    __device__ static double abs(double v) { return __builtin_fabs(v); }
     __device__ static double sqrt(double v) { return ::sqrt(v); }
     __device__ static double pow_m15_sq(double err2) { return ::pow(err2, -0.1); }
 };
@@ -89,6 +91,34 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Cross-lane moves inside a row of 16 lanes (DPP): quad butterflies for
+// masks 1 and 2, the half-row and row mirrors pair groups of 4 and 8 lanes.
+enum : int { kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140 };
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+// Sum over the aligned group of lpt lanes (a power of two); every lane of
+// the group gets the same bits, since each level adds two equal partial sums
+// in either order.  Called from wave-uniform control flow only.
+template <typename T>
+__device__ __forceinline__ T group_reduce(T v, int lpt) {
+    if (lpt >= 2) v += dpp_mov<kDppXor1>(v);
+    if (lpt >= 4) v += dpp_mov<kDppXor2>(v);
+    if (lpt >= 8) v += dpp_mov<kDppHalfMirror>(v);
+    if (lpt >= 16) v += dpp_mov<kDppMirror>(v);
+    if (lpt >= 32) v += __shfl_xor(v, 16);
+    if (lpt >= 64) v += __shfl_xor(v, 32);
+    return v;
 }
 
 enum : int { kRunning = -1 };
@@ -191,14 +221,12 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
         for (int q = 0; q < GPL; ++q) f[q] = gG[q] * (ld(g_pe[q]) * O::rcp(ld(g_pb[q]))) - gk[q] * yv[q];
     };
 
-    auto group_sum = [&](double v) {
-        for (int m = 1; m < lpt; m <<= 1) v += __shfl_xor(v, m);
-        return v;
+    auto group_sum = [&](double v) { return group_reduce(v, lpt); };
+    // Steady-state test |f_i| <= ss_atol + ss_rtol k_i |x_i|, compared in FP64.
+    auto is_steady = [&](R f, R kv, R xv) {
+        return __builtin_fabs((double)f) <= c.ss_atol + c.ss_rtol * (double)kv * __builtin_fabs((double)xv);
     };
-    auto group_sumf = [&](float v) {
-        for (int m = 1; m < lpt; m <<= 1) v += __shfl_xor(v, m);
-        return v;
-    };
+    auto group_sumf = [&](float v) { return group_reduce(v, lpt); };
     auto group_all = [&](bool p) { return ((__ballot(p) >> gshift) & glow) == glow; };
 
     // Write the end-of-trajectory record and free the group.
@@ -281,22 +309,30 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
             const float* Tp = RAC_DF(T) + p;
             const float* Lp = RAC_DF(lam) + p;
             const uint8_t* Np = RAC_DF(n) + p;
+            // Only the loads are conditional: padding slots take T = lam = n = 1
+            // and the sink, which the same formulas turn into beta' = 1 and
+            // delta' = 0 (every array element is written on one path, which
+            // keeps the arrays in registers).
 #pragma unroll
             for (int s = 0; s < EPL; ++s) {
                 asm volatile("" ::: "memory");
                 const int pk = s < stride ? lane_edge[s] : -1;
+                float Tv = 1.0f, Lv = 1.0f;
+                int nv = 1;
+                uint32_t xa = sink;
                 if (pk >= 0) {
                     const int e = pk & 0xffff, src = pk >> 16;
-                    const R Tv = (R)Tp[e * P];
-                    const R sl = O::sqrt((R)Lp[e * P]);
-                    e_xa[s] = (wave_elem + (uint32_t)(src * n_groups + g)) * SZ;
-                    e_invT[s] = O::edge_t(Tv);
-                    e_n[s] = O::to_n((int)Np[e * P]);
-                    e_b[s] = sl;
-                    e_d[s] = (R)1 / sl - sl;
-                } else {
-                    e_xa[s] = sink; e_invT[s] = 0; e_b[s] = 1; e_d[s] = 0; e_n[s] = O::to_n(1);
+                    Tv = Tp[e * P];
+                    Lv = Lp[e * P];
+                    nv = Np[e * P];
+                    xa = (wave_elem + (uint32_t)(src * n_groups + g)) * SZ;
                 }
+                const R sl = O::sqrt((R)Lv);
+                e_xa[s] = xa;
+                e_invT[s] = O::edge_t((R)Tv, nv);
+                e_n[s] = O::to_n(nv);
+                e_b[s] = sl;
+                e_d[s] = (R)1 / sl - sl;
             }
             const float* Gp = RAC_DF(G) + p;
             const float* Kp = RAC_DF(k) + p;
@@ -305,35 +341,37 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
             const int32_t* gene_row = RAC_DF(gene_row);
             const int8_t* sign = RAC_DF(sign);
 #undef RAC_DF
+            // As for edges: conditional loads, one unconditional write per
+            // element; padding genes get G = k = 0 and the sink.
 #pragma unroll
             for (int q = 0; q < GPL; ++q) {
                 asm volatile("" ::: "memory");
                 const int gene = r + q * lpt;
-                if (gene < n_genes) {
-                    const R Gv = (R)Gp[gene * P];
-                    const R kv = (R)Kp[gene * P];
+                const bool real = gene < n_genes;
+                R Gv = 0, kv = 1, gf = 0, u = 0;
+                int row = 0;
+                if (real) {
+                    Gv = (R)Gp[gene * P];
+                    kv = (R)Kp[gene * P];
                     // Fold each row's sqrt(lam) (and, for activation
                     // over lambda, 1/lam) into the production rate.
-                    R gf = Gv;
+                    gf = Gv;
                     for (int e = row_ptr[gene]; e < row_ptr[gene + 1]; ++e) {
                         const R sl = O::sqrt((R)Lp[e * P]);
                         gf *= (sign[e] > 0 && c.divide) ? (R)1 / sl : sl;
                     }
-                    const int row = gene_row[gene];
-                    const int rl = row & 0xff, pb = (row >> 8) & 0xff, pe = (row >> 16) & 0xff;
-                    const uint32_t rowlane = (uint32_t)(gshift + rl);
-                    g_id[q] = gene;
-                    g_wa[q] = (wave_elem + (uint32_t)(gene * n_groups + g)) * SZ;
-                    g_pb[q] = (wave_elem + 64 * GPL + (uint32_t)pb * 64 + rowlane) * SZ;
-                    g_pe[q] = (wave_elem + 64 * GPL + (uint32_t)pe * 64 + rowlane) * SZ;
-                    gG[q] = gf;
-                    gk[q] = kv;
-                    const R u = (R)icp[gene];
-                    x[q] = c.ic_absolute ? u : u * Gv / kv;
-                } else {
-                    g_id[q] = -1; g_wa[q] = sink; g_pb[q] = pre_base; g_pe[q] = pre_base;
-                    gG[q] = 0; gk[q] = 0; x[q] = 0;
+                    row = gene_row[gene];
+                    u = (R)icp[gene];
                 }
+                const int rl = row & 0xff, pb = (row >> 8) & 0xff, pe = (row >> 16) & 0xff;
+                const uint32_t rowlane = (uint32_t)(gshift + rl);
+                g_id[q] = real ? gene : -1;
+                g_wa[q] = real ? (wave_elem + (uint32_t)(gene * n_groups + g)) * SZ : sink;
+                g_pb[q] = real ? (wave_elem + 64 * GPL + (uint32_t)pb * 64 + rowlane) * SZ : pre_base;
+                g_pe[q] = real ? (wave_elem + 64 * GPL + (uint32_t)pe * 64 + rowlane) * SZ : pre_base;
+                gG[q] = gf;
+                gk[q] = real ? kv : (R)0;
+                x[q] = c.ic_absolute ? u : u * Gv / kv;
             }
             t = c.t0;
             t_stop = TS ? a.t_out[a.n_t - 1] : c.t_end;
@@ -441,8 +479,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
                     const float isc = 1.0f / ((float)c.atol + (float)c.rtol * fabsf(xv));
                     s0 += (xv * isc) * (xv * isc);
                     s1 += (fv * isc) * (fv * isc);
-                    steady = steady && fabs((double)kk[1][q]) <=
-                                           c.ss_atol + c.ss_rtol * (double)gk[q] * fabs((double)x[q]);
+                    steady = steady && is_steady(kk[1][q], gk[q], x[q]);
                 }
             }
             const bool all_fin = group_all(fin);
@@ -539,11 +576,11 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
             for (int l = 2; l < 7; ++l) e += (R)kErr[l] * kk[l][q];
             // Scaled error e_i / (atol + rtol max(|x_i|, |x_new,i|)); the ratio
             // in R, its square accumulated in FP64.
-            const R ax = x[q] < 0 ? -x[q] : x[q], an = y[q] < 0 ? -y[q] : y[q];
+            const R ax = O::abs(x[q]), an = O::abs(y[q]);
             const R sc = (R)c.atol + (R)c.rtol * (ax > an ? ax : an);
             const double rq = g_id[q] >= 0 ? (double)(hR * e * O::rcp(sc)) : 0.0;
             serr += rq * rq;
-            fin = fin && (g_id[q] < 0 || __builtin_isfinite((double)y[q]));
+            fin = fin && (g_id[q] < 0 || __builtin_isfinite(y[q]));
         }
         // Accept iff the RMS error is <= 1, i.e. its square is; one factor
         // 0.9 err^(-1/5), clamped to [0.2, 10] after an accepted step that did
@@ -594,9 +631,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
             for (int q = 0; q < GPL; ++q) {
                 x[q] = y[q];
                 kk[0][q] = kk[6][q];
-                steady = steady && (g_id[q] < 0 ||
-                                    fabs((double)kk[0][q]) <=
-                                        c.ss_atol + c.ss_rtol * (double)gk[q] * fabs((double)x[q]));
+                steady = steady && (g_id[q] < 0 || is_steady(kk[0][q], gk[q], x[q]));
             }
         }
         const bool all_steady = group_all(steady);
