@@ -32,7 +32,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "RACIPE ODE solves/s to steady state, batched FP32 vs plain FP64; p50/p99 latency"
-PEAK_FP32 = 157.3e12   # MI355X FP32 vector (published)
+PEAK_FP32 = 157.3e12   # MI355X FP32 vector (published; needs packed FP32)
+# FP32 FMA issue without packed instructions, which these kernels are built
+# without: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz.
+PEAK_FP32_UNPACKED = 78.6e12
 PEAK_HBM = 8.0e12
 
 
@@ -205,6 +208,7 @@ def bench_er10(args, torch, rp, flops, inputs):
         "roofline": {
             "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32,
+            "frac_of_unpacked_fma_peak": achieved / PEAK_FP32_UNPACKED,
             "traffic": measured_traffic("er10_1e6_fp32") if default_cfg else None,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "algorithmic_bytes_per_launch": nbytes,
@@ -298,7 +302,9 @@ def bench_uneven64(args, torch, rp, flops, inputs):
                            "trajectories": n_traj},
                 "roofline": {"bound": "alu", "achieved": fl / (lat.mean() * 1e-3) / 1e12,
                              "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                             "frac": fl / (lat.mean() * 1e-3) / PEAK_FP32, "traffic": None},
+                             "frac": fl / (lat.mean() * 1e-3) / PEAK_FP32,
+                             "frac_of_unpacked_fma_peak": fl / (lat.mean() * 1e-3) / PEAK_FP32_UNPACKED,
+                             "traffic": None},
                 "plain_fp64": {"value": v64, "unit": "solves/s",
                                "what": "FP64, one launch per network"},
                 "speedup_fp32_vs_fp64": v32 / v64})
@@ -340,7 +346,9 @@ def bench_core22ts(args, torch, rp, flops, inputs):
                            "lanes_per_traj": T.auto_lanes()},
                 "roofline": {"bound": "alu", "achieved": fl / (lat.mean() * 1e-3) / 1e12,
                              "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                             "frac": fl / (lat.mean() * 1e-3) / PEAK_FP32, "traffic": None,
+                             "frac": fl / (lat.mean() * 1e-3) / PEAK_FP32,
+                             "frac_of_unpacked_fma_peak": fl / (lat.mean() * 1e-3) / PEAK_FP32_UNPACKED,
+                             "traffic": None,
                              "algorithmic_bytes_per_launch": nbytes,
                              "hbm_frac": nbytes / (lat.mean() * 1e-3) / PEAK_HBM},
                 "plain_fp64": {"value": v64, "unit": "solves/s"},
