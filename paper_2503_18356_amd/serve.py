@@ -149,15 +149,20 @@ class GpuExecutor:
     """Runs admitted requests on the GPU through rac_server step batches, one
     server per kernel class (lanes per trajectory, slot shape).
 
-    A network joins an existing class of its lane count whose shape is at
-    least its own when that costs at most ``merge_slack`` times the per-step
-    work of its own shape (padding slots compute factors of exactly one), so
-    a mix of networks runs in few classes.  Classes share a small pool of
-    streams; each loop iteration enqueues one batch per active class and the
-    finished counts of all classes, then waits once."""
+    A network joins an existing class (any lane count it fits, with a shape
+    at least its own at that lane count) when the class costs at most
+    ``merge_slack`` times the per-trajectory work of the network's own choice
+    (padding slots compute factors of exactly one), so a mix of networks runs
+    in few classes.  Classes share a small pool of
+    streams.  The loop is pipelined: each iteration enqueues one batch per
+    active class and a copy of every class's finished counts into pinned
+    memory, then reads the counts the previous iteration copied (waiting on
+    its event), so the GPU already holds the next batch while the host
+    admits and retires requests.  A request is seen finished one batch after
+    its last trajectory ends."""
 
     def __init__(self, opts=None, batch_steps: int = 256, max_requests: int = 65536,
-                 device="cuda", keep_results: bool = True, merge_slack: float = 1.5,
+                 device="cuda", keep_results: bool = True, merge_slack: float = 2.0,
                  n_streams: int = 4):
         import torch
         from . import racipe as rp
@@ -171,30 +176,38 @@ class GpuExecutor:
         self.merge_slack = merge_slack
         self.streams = [torch.cuda.Stream(device=device) for _ in range(max(1, n_streams))]
         self.classes: dict[tuple, dict] = {}
+        self.pending = None  # (event, [(class, lo, hi, buffer)]) of the last poll
+        self.polls = 0
 
     @staticmethod
-    def slot_cost(epl: int, gpl: int) -> float:
-        # Per-step issue cost model of a kernel shape (edge and gene slots).
-        return 14.0 * epl + 25.0 * gpl + 40.0
+    def slot_cost(lanes: int, epl: int, gpl: int) -> float:
+        # Per-trajectory issue cost model of a kernel class: lanes per
+        # trajectory times the per-lane work of its edge and gene slots.
+        return lanes * (14.0 * epl + 25.0 * gpl + 40.0)
 
     def _class(self, T):
-        lanes = T.auto_lanes(self.rp.FP32)
-        epl, gpl = T.shape(lanes, self.rp.FP32)
-        own = self.slot_cost(epl, gpl)
+        fp32 = self.rp.FP32
+        lanes = T.auto_lanes(fp32)
+        epl, gpl = T.shape(lanes, fp32)
+        own = self.slot_cost(lanes, epl, gpl)
         best = None
-        for key, cl in self.classes.items():
+        for key in self.classes:
             kl, ke, kg = key
-            if kl == lanes and ke >= epl and kg >= gpl:
-                c = self.slot_cost(ke, kg)
+            if not T.lanes_supported(kl, fp32):
+                continue
+            ne, ng = T.shape(kl, fp32)
+            if ke >= ne and kg >= ng:
+                c = self.slot_cost(kl, ke, kg)
                 if c <= self.merge_slack * own and (best is None or c < best[0]):
                     best = (c, key)
         if best is not None:
             return best[1], self.classes[best[1]]
         key = (lanes, epl, gpl)
         srv = self.rp.StepServer(self.opts, lanes, epl, gpl, self.max_requests, self.batch_steps)
-        counts = self.torch.zeros(self.max_requests, dtype=self.torch.int32, pin_memory=True)
+        bufs = [self.torch.zeros(self.max_requests, dtype=self.torch.int32, pin_memory=True)
+                for _ in range(2)]
         self.classes[key] = {"server": srv, "stream": self.streams[len(self.classes) % len(self.streams)],
-                             "active": {}, "counts_t": counts, "counts": counts.numpy()}
+                             "active": {}, "bufs": bufs, "counts": [b.numpy() for b in bufs]}
         return key, self.classes[key]
 
     def start(self, req: Request):
@@ -217,21 +230,36 @@ class GpuExecutor:
                 cl["server"].step(stream=cl["stream"])
 
     def finished(self) -> list[int]:
+        torch = self.torch
+        # Enqueue this iteration's counts copies (after the batches just
+        # launched) and record one event behind them on every stream used.
+        which = self.polls % 2
+        self.polls += 1
         polled = []
         for cl in self.classes.values():
             act = cl["active"]
             if act:
                 lo, hi = min(act), max(act) + 1
-                cl["server"].done_counts(lo, hi - lo, cl["counts"], stream=cl["stream"])
-                polled.append((cl, lo))
-        for st in {id(cl["stream"]): cl["stream"] for cl, _ in polled}.values():
-            st.synchronize()
+                cl["server"].done_counts(lo, hi - lo, cl["counts"][which], stream=cl["stream"])
+                polled.append((cl, lo, hi, which))
+        events = []
+        for st in {id(cl["stream"]): cl["stream"] for cl, *_ in polled}.values():
+            ev = torch.cuda.Event()
+            ev.record(st)
+            events.append(ev)
+        prev, self.pending = self.pending, (events, polled)
+        if prev is None:
+            return []
+        # Read what the previous iteration copied.
+        for ev in prev[0]:
+            ev.synchronize()
         out = []
-        for cl, lo in polled:
+        for cl, lo, hi, w in prev[1]:
             act = cl["active"]
-            for srv_rid in list(act):
-                req = act[srv_rid]
-                if cl["counts"][srv_rid - lo] >= req.n_traj:
+            cnt = cl["counts"][w]
+            for srv_rid in range(lo, hi):
+                req = act.get(srv_rid)
+                if req is not None and cnt[srv_rid - lo] >= req.n_traj:
                     out.append(req.rid)
                     del act[srv_rid]
         return out
