@@ -47,7 +47,7 @@ class _Opts(C.Structure):
                 ("atol", C.c_double), ("ss_atol", C.c_double), ("ss_rtol", C.c_double),
                 ("h0", C.c_double), ("max_steps", C.c_int64),
                 ("divide_act_by_lambda", C.c_int32), ("stop_at_steady", C.c_int32),
-                ("ic_absolute", C.c_int32)]
+                ("ic_absolute", C.c_int32), ("method", C.c_int32)]
 
 
 class _Problem(C.Structure):
@@ -86,6 +86,8 @@ def load(path: str):
     L.orc_rk4.restype = C.c_int
     L.orc_dp5_fixed.argtypes = [C.POINTER(_Problem), C.POINTER(_Opts), i64, i64, vp, vp]
     L.orc_dp5_fixed.restype = C.c_int
+    L.orc_tableau.argtypes = [i32, vp, vp, vp, vp]
+    L.orc_tableau.restype = C.c_int
     return L
 
 
@@ -188,6 +190,17 @@ def sample(net: Network, seed: int, n_sets: int, n_ic: int, set_begin: int = 0,
     return Params(G, k, T, lam, n, ic)
 
 
+DP5, TSIT5 = 0, 1
+
+
+def tableau(method: int):
+    """(A[7][7], b, bh, c) of the oracle's 5(4) pair for a method."""
+    a = np.zeros((7, 7)); b = np.zeros(7); bh = np.zeros(7); c = np.zeros(7)
+    if lib().orc_tableau(method, _ptr(a), _ptr(b), _ptr(bh), _ptr(c)) != 0:
+        raise ValueError(f"unknown method {method}")
+    return a, b, bh, c
+
+
 @dataclass
 class Opts:
     t0: float = 0.0
@@ -201,6 +214,7 @@ class Opts:
     divide_act_by_lambda: int = 1
     stop_at_steady: int = 0
     ic_absolute: int = 0
+    method: int = 0  # DP5 or TSIT5
 
     def c(self) -> _Opts:
         return _Opts(*[getattr(self, f[0]) for f in _Opts._fields_])

@@ -190,6 +190,7 @@ void orc_default_opts(orc_opts* o) {
     o->t0 = 0.0; o->t_end = 200.0; o->rtol = 1e-6; o->atol = 1e-9;
     o->ss_atol = 1e-6; o->ss_rtol = 0.0; o->h0 = 0.0; o->max_steps = 100000;
     o->divide_act_by_lambda = 1; o->stop_at_steady = 0; o->ic_absolute = 0;
+    o->method = ORC_DP5;
 }
 
 /* Shifted Hill function H^S(B, B0, n, lambda), Eq. 2. */
@@ -236,11 +237,71 @@ static const double DP_B[7] = {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0
 static const double DP_BH[7] = {5179.0 / 57600, 0, 7571.0 / 16695, 393.0 / 640,
                                 -92097.0 / 339200, 187.0 / 2100, 1.0 / 40};
 
+/* ------------------------------------------------------------------------ */
+/* Tsitouras 5(4) tableau (Ch. Tsitouras, Comput. Math. Appl. 62 (2011),      */
+/* Table 1), the solver the paper's library uses (Sec. 2.1.3).  Nodes c2..c5  */
+/* are 0.161, 0.327, 0.9 and 0.98002554...; c6 = c7 = 1.  The last row is the */
+/* fifth-order solution; the differences b - bh are the published error      */
+/* weights.                                                                  */
+/* ------------------------------------------------------------------------ */
+static const double TS_A[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {0.161, 0, 0, 0, 0, 0},
+    {-0.008480655492356989, 0.335480655492357, 0, 0, 0, 0},
+    {2.897153057105493, -6.359448489975075, 4.3622954328695815, 0, 0, 0},
+    {5.325864828439257, -11.748883564062828, 7.4955393428898365, -0.09249506636175525, 0, 0},
+    {5.86145544294642, -12.92096931784711, 8.159367898576159, -0.071584973281401,
+     -0.028269050394068383, 0},
+    {0.09646076681806523, 0.01, 0.4798896504144996, 1.379008574103742, -3.290069515436081,
+     2.324710524099774},
+};
+static const double TS_E[7] = {-0.00178001105222577714, -0.0008164344596567469, 0.007880878010261995,
+                               -0.1447110071732629,     0.5823571654525552,     -0.45808210592918697,
+                               0.015151515151515152};
+
+typedef struct {
+    double a[7][7];
+    double b[7], bh[7], c[7];
+} orc_rk;
+
+static void orc_rk_get(int32_t method, orc_rk* t) {
+    memset(t, 0, sizeof(*t));
+    for (int i = 0; i < 7; ++i) {
+        for (int j = 0; j < 6; ++j) t->a[i][j] = method == ORC_TSIT5 ? TS_A[i][j] : DP_A[i][j];
+        double ci = 0.0;
+        for (int j = 0; j < i; ++j) ci += t->a[i][j];
+        t->c[i] = ci;
+    }
+    for (int j = 0; j < 7; ++j) {
+        if (method == ORC_TSIT5) {
+            t->b[j] = j < 6 ? TS_A[6][j] : 0.0;
+            t->bh[j] = t->b[j] - TS_E[j];
+        } else {
+            t->b[j] = DP_B[j];
+            t->bh[j] = DP_BH[j];
+        }
+    }
+}
+
+int orc_tableau(int32_t method, double* a, double* b, double* bh, double* c) {
+    if (method != ORC_DP5 && method != ORC_TSIT5) return -1;
+    orc_rk t;
+    orc_rk_get(method, &t);
+    for (int i = 0; i < 7; ++i) {
+        for (int j = 0; j < 7; ++j) a[i * 7 + j] = t.a[i][j];
+        b[i] = t.b[i];
+        bh[i] = t.bh[i];
+        c[i] = t.c[i];
+    }
+    return 0;
+}
+
 typedef struct {
     const orc_problem* pb;
     const orc_opts* o;
     int64_t p;
     int N;
+    orc_rk rk;
     double* k[7];
     double* y;
     double* xn;
@@ -248,6 +309,7 @@ typedef struct {
 
 static void orc_stepper_init(orc_stepper* s, const orc_problem* pb, const orc_opts* o, int64_t p) {
     s->pb = pb; s->o = o; s->p = p; s->N = pb->n_genes;
+    orc_rk_get(o->method, &s->rk);
     for (int i = 0; i < 7; ++i) s->k[i] = (double*)calloc((size_t)s->N, sizeof(double));
     s->y = (double*)calloc((size_t)s->N, sizeof(double));
     s->xn = (double*)calloc((size_t)s->N, sizeof(double));
@@ -259,15 +321,16 @@ static void orc_stepper_free(orc_stepper* s) {
     free(s->xn);
 }
 
-/* One DP5 attempt from (x, f=k1) with step h.  Writes the 5th-order result to
- * s->xn, its derivative to s->k[6] (FSAL), and returns the RMS error norm. */
-static double orc_dp5_attempt(orc_stepper* s, const double* x, const double* f, double h) {
+/* One attempt of the 5(4) pair from (x, f=k1) with step h.  Writes the
+ * 5th-order result to s->xn, its derivative to s->k[6] (FSAL), and returns
+ * the RMS error norm. */
+static double orc_rk_attempt(orc_stepper* s, const double* x, const double* f, double h) {
     const int N = s->N;
     memcpy(s->k[0], f, sizeof(double) * (size_t)N);
     for (int st = 1; st < 7; ++st) {
         for (int i = 0; i < N; ++i) {
             double acc = 0.0;
-            for (int l = 0; l < st; ++l) acc += DP_A[st][l] * s->k[l][i];
+            for (int l = 0; l < st; ++l) acc += s->rk.a[st][l] * s->k[l][i];
             s->y[i] = x[i] + h * acc;
         }
         orc_rhs(s->pb, s->p, s->o->divide_act_by_lambda, s->y, s->k[st]);
@@ -277,7 +340,7 @@ static double orc_dp5_attempt(orc_stepper* s, const double* x, const double* f, 
     double sum = 0.0;
     for (int i = 0; i < N; ++i) {
         double e = 0.0;
-        for (int l = 0; l < 7; ++l) e += (DP_B[l] - DP_BH[l]) * s->k[l][i];
+        for (int l = 0; l < 7; ++l) e += (s->rk.b[l] - s->rk.bh[l]) * s->k[l][i];
         e *= h;
         double ax = fabs(x[i]), an = fabs(s->xn[i]);
         double sc = s->o->atol + s->o->rtol * (ax > an ? ax : an);
@@ -388,7 +451,7 @@ static orc_result orc_integrate_one(const orc_problem* pb, const orc_opts* o, in
         int clipped = 0;
         double hs = h;
         if (t + hs >= t_next) { hs = t_next - t; clipped = 1; }
-        double err = orc_dp5_attempt(&s, x, f, hs);
+        double err = orc_rk_attempt(&s, x, f, hs);
         int ok = isfinite(err) && err <= 1.0 && orc_all_finite(s.xn, N);
         if (ok) {
             res.n_acc++;
@@ -556,10 +619,14 @@ static int orc_check_problem(const orc_problem* pb) {
     return 0;
 }
 
+static int orc_check_method(const orc_opts* o) {
+    return (o->method == ORC_DP5 || o->method == ORC_TSIT5) ? 0 : -1;
+}
+
 int orc_steady_states(const orc_problem* pb, const orc_opts* o, const int64_t* traj_ids,
                       int64_t n_traj, int32_t n_threads, double* x_out, double* t_final,
                       int8_t* status, int32_t* n_acc, int32_t* n_rej) {
-    if (orc_check_problem(pb)) return -1;
+    if (orc_check_problem(pb) || orc_check_method(o)) return -1;
     orc_job jb;
     memset(&jb, 0, sizeof(jb));
     jb.kind = ORC_JOB_STEADY; jb.pb = pb; jb.o = o; jb.ids = traj_ids;
@@ -580,7 +647,7 @@ static int orc_check_times(const orc_opts* o, const double* t_out, int32_t n_t) 
 int orc_time_series(const orc_problem* pb, const orc_opts* o, const double* t_out, int32_t n_t,
                     const int64_t* traj_ids, int64_t n_traj, int32_t n_threads, double* x_out,
                     double* t_final, int8_t* status, int32_t* n_acc, int32_t* n_rej) {
-    if (orc_check_problem(pb) || orc_check_times(o, t_out, n_t)) return -1;
+    if (orc_check_problem(pb) || orc_check_method(o) || orc_check_times(o, t_out, n_t)) return -1;
     orc_job jb;
     memset(&jb, 0, sizeof(jb));
     jb.kind = ORC_JOB_TS; jb.pb = pb; jb.o = o; jb.ids = traj_ids;
@@ -603,7 +670,7 @@ int orc_rk4(const orc_problem* pb, const orc_opts* o, double h, const double* t_
 
 int orc_dp5_fixed(const orc_problem* pb, const orc_opts* o, int64_t traj, int64_t n_steps,
                   double* x_out, double* err_last) {
-    if (orc_check_problem(pb) || n_steps < 1) return -1;
+    if (orc_check_problem(pb) || orc_check_method(o) || n_steps < 1) return -1;
     const int N = pb->n_genes;
     int64_t p = traj / pb->n_ic, c = traj % pb->n_ic;
     orc_stepper s;
@@ -615,7 +682,7 @@ int orc_dp5_fixed(const orc_problem* pb, const orc_opts* o, int64_t traj, int64_
     double err = 0.0;
     for (int64_t st = 0; st < n_steps; ++st) {
         orc_rhs(pb, p, o->divide_act_by_lambda, x, f);
-        err = orc_dp5_attempt(&s, x, f, h);
+        err = orc_rk_attempt(&s, x, f, h);
         memcpy(x, s.xn, sizeof(double) * (size_t)N);
     }
     memcpy(x_out, x, sizeof(double) * (size_t)N);

@@ -59,7 +59,16 @@ typedef struct {
     int32_t divide_act_by_lambda; /* 1 = Eq. 1 as printed */
     int32_t stop_at_steady;       /* time-series mode only */
     int32_t ic_absolute;          /* ic holds absolute values, not fractions of G/k */
+    int32_t method;               /* ORC_DP5 or ORC_TSIT5 */
 } orc_opts;
+
+/* Embedded explicit Runge-Kutta 5(4) pairs with 7 stages, first same as last. */
+enum { ORC_DP5 = 0, ORC_TSIT5 = 1 };
+
+/* The tableau of a method: a[7*7] (row i holds the weights of k_1..k_i in the
+ * input of stage i+1), b[7] fifth-order weights, bh[7] fourth-order
+ * weights, c[7] nodes.  Returns -1 for an unknown method. */
+int orc_tableau(int32_t method, double* a, double* b, double* bh, double* c);
 
 void orc_default_opts(orc_opts* o);
 
@@ -100,8 +109,9 @@ int orc_time_series(const orc_problem* pb, const orc_opts* o, const double* t_ou
 int orc_rk4(const orc_problem* pb, const orc_opts* o, double h, const double* t_out, int32_t n_t,
             const int64_t* traj_ids, int64_t n_traj, int32_t n_threads, double* x_out);
 
-/* Fixed-step DP5 (no control) from t0 to t_end with n_steps equal steps, for
- * one trajectory; also returns the embedded error estimate of the last step. */
+/* Fixed-step run of o->method (no control) from t0 to t_end with n_steps
+ * equal steps, for one trajectory; also returns the embedded error estimate
+ * of the last step. */
 int orc_dp5_fixed(const orc_problem* pb, const orc_opts* o, int64_t traj, int64_t n_steps,
                   double* x_out, double* err_last);
 

@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_pins as pins
+from tests import test_oracle_tsit5 as tsit5
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle")
 
@@ -48,6 +49,12 @@ MUTATIONS = [
      [pins.test_philox_matches_numpy_bit_generator]),
     ("hill exponent", "double b = pow(B, n);", "double b = pow(B, n + 1);",
      [pins.test_hill_half_point_for_known_power]),
+    ("tsit5 a53 digit", "7.4955393428898365", "7.4955393428998365",
+     [tsit5.test_tableau_order_conditions, tsit5.test_tsit5_fifth_order_on_linear_decay]),
+    ("tsit5 error weight e4", "-0.1447110071732629,", "-0.1474110071732629,",
+     [tsit5.test_tableau_order_conditions]),
+    ("tsit5 row 7 weight b6", "2.324710524099774},", "2.324701524099774},",
+     [tsit5.test_tableau_order_conditions]),
 ]
 
 
@@ -85,6 +92,8 @@ def _fails(fn):
             fn(n=2)
         elif "builder" in params:
             fn(builder=pins.inputs.toggle_switch)
+        elif "method" in params:
+            fn(method=oracle.TSIT5)
         else:
             fn()
     except AssertionError:
