@@ -64,6 +64,11 @@ typedef enum {
 
 typedef enum { RAC_FP32 = 0, RAC_FP64 = 1 } rac_precision;
 
+/* Embedded Runge-Kutta 5(4) pair of the integrator.  RAC_DP5: Dormand-Prince
+ * (Hairer, Norsett, Wanner I, Table 5.2).  RAC_TSIT5: Tsitouras (2011), the
+ * solver the paper's library uses (Sec. 2.1.3). */
+typedef enum { RAC_DP5 = 0, RAC_TSIT5 = 1 } rac_method;
+
 /* Message for the last failing call on this thread ("" if none). */
 const char* rac_last_error(void);
 
@@ -177,6 +182,11 @@ typedef struct {
                                the work queue once this many of its trajectory
                                groups are free (each refill costs the wave two
                                right-hand sides); always 1 near the queue end */
+    int32_t method;         /* RAC_DP5 (default) or RAC_TSIT5.  Both use the same
+                               step control; time series interpolate inside a step
+                               with a continuous extension of order 4 (DP5: Hairer,
+                               Norsett, Wanner I, Sec. II.6; Tsit5: quartic weights
+                               solving the order conditions, C1 at both ends) */
 } rac_solver_opts;
 
 /* Defaults for a precision. */
@@ -254,7 +264,8 @@ rac_status rac_steady_states_batch(const rac_batch_item* items, int32_t n_items,
 typedef struct rac_server rac_server;
 
 /* EINVAL: bad opts, lanes_per_traj < 1, max_requests < 1, batch_steps < 1.
- * EUNSUPPORTED: precision other than RAC_FP32, or no compiled (epl, gpl).
+ * EUNSUPPORTED: precision other than RAC_FP32, method other than RAC_DP5, or
+ * no compiled (epl, gpl).
  * ENOMEM: device allocation failed. */
 rac_status rac_server_create(const rac_solver_opts* opts, int32_t epl, int32_t gpl,
                              int32_t max_requests, int32_t batch_steps, rac_server** out);

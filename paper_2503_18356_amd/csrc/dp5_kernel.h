@@ -1,12 +1,15 @@
-// The persistent DP5(4) ensemble kernel, templated on the state precision R,
-// the compiled edge-slot and gene-slot budgets (EPL, GPL) and the output mode
-// (steady state or time series).  Included by the per-precision translation
+// The persistent Runge-Kutta 5(4) ensemble kernel, templated on the state
+// precision R, the compiled edge-slot and gene-slot budgets (EPL, GPL), the
+// output mode (steady state or time series), the serving variant and the
+// method (Dormand-Prince or Tsitouras pair).  Included by the translation
 // units that instantiate it.
 #pragma once
 
 #include "kernel_common.h"
 
 namespace rac {
+
+enum : int { kDP5 = RAC_DP5, kTsit5 = RAC_TSIT5 };
 
 // Dormand & Prince (1980) 5(4) tableau (Hairer, Norsett, Wanner I, Table 5.2).
 // Row s holds the weights of k_1..k_s in the input of stage s+1; row 6 is the
@@ -33,6 +36,46 @@ __device__ constexpr double kDense[7] = {
     87487479700.0 / 32700410799.0,  -10690763975.0 / 1880347072.0,
     701980252875.0 / 199316789632.0, -1453857185.0 / 822651844.0,
     69997945.0 / 29380423.0};
+
+// Tsitouras (2011) 5(4) pair, the method of the paper's library: stage
+// weights (row 6 is the fifth-order solution, first same as last) and the
+// fifth- minus fourth-order weights.
+__device__ constexpr double kTsA[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {0.161, 0, 0, 0, 0, 0},
+    {-0.008480655492356989, 0.335480655492357, 0, 0, 0, 0},
+    {2.897153057105493, -6.359448489975075, 4.3622954328695815, 0, 0, 0},
+    {5.325864828439257, -11.748883564062828, 7.4955393428898365, -0.09249506636175525, 0, 0},
+    {5.86145544294642, -12.92096931784711, 8.159367898576159, -0.071584973281401,
+     -0.028269050394068383, 0},
+    {0.09646076681806523, 0.01, 0.4798896504144996, 1.379008574103742, -3.290069515436081,
+     2.324710524099774},
+};
+__device__ constexpr double kTsErr[7] = {-0.00178001105222577714, -0.0008164344596567469,
+                                         0.007880878010261995,    -0.1447110071732629,
+                                         0.5823571654525552,      -0.45808210592918697,
+                                         0.015151515151515152};
+
+// Continuous extension for Tsit5 time series: x(t + th h) = x + h sum_i b_i(th)
+// k_i with b_i(th) = sum_p kTsDense[i][p] th^(p+1).  The weights satisfy the
+// order conditions of orders 1..4 as identities in th, equal the step's
+// weights at th = 1 and match f at both ends (local error O(h^5)); the one
+// remaining freedom is the minimum-norm choice (tsit5_dense.py derives them
+// from kTsA).
+__device__ constexpr double kTsDense[7][4] = {
+    {1.0, -2.631639750604532, 2.649122568481329, -0.9210220510587314},
+    {0.0, 0.1922746789549526, -0.3445493579099373, 0.16227467895497885},
+    {0.0, 3.345581016079935, -4.771603430501868, 1.9059120648364314},
+    {0.0, -1.6743637698306488, 8.864761836076259, -5.811389492141867},
+    {0.0, -5.698194445881719, -1.7638891699808519, 4.172014100426498},
+    {0.0, 6.090496396744703, -2.8821506970903297, -0.8836351755546025},
+    {0.0, 0.3758458745373101, -1.7516917490746, 1.3758458745372943},
+};
+
+template <int M>
+__device__ constexpr double tab_a(int s, int l) { return M == kTsit5 ? kTsA[s][l] : kA[s][l]; }
+template <int M>
+__device__ constexpr double tab_e(int l) { return M == kTsit5 ? kTsErr[l] : kErr[l]; }
 
 // Transcendentals: hardware v_log/v_exp/v_rcp for FP32; exact routines and
 // an integer power for FP64.
@@ -134,7 +177,7 @@ struct LdsLayout {
     static constexpr int kWaveElems = 64 * kSlots;
 };
 
-template <typename R, int EPL, int GPL, bool TS, bool BOUNDED = false>
+template <typename R, int EPL, int GPL, bool TS, bool BOUNDED = false, int M = kDP5>
 __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
     static_assert(!(TS && BOUNDED), "serving step batches run in steady-state mode");
     using O = Ops<R>;
@@ -558,10 +601,10 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
         for (int st_ = 1; st_ < 7; ++st_) {
 #pragma unroll
             for (int q = 0; q < GPL; ++q) {
-                R acc = (R)kA[st_][0] * kk[0][q];
+                R acc = (R)tab_a<M>(st_, 0) * kk[0][q];
 #pragma unroll
                 for (int l = 1; l < st_; ++l)
-                    if (kA[st_][l] != 0.0) acc += (R)kA[st_][l] * kk[l][q];
+                    if (tab_a<M>(st_, l) != 0.0) acc += (R)tab_a<M>(st_, l) * kk[l][q];
                 y[q] = x[q] + hR * acc;
             }
             rhs(y, kk[st_]);
@@ -571,9 +614,10 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
         bool fin = true;
 #pragma unroll
         for (int q = 0; q < GPL; ++q) {
-            R e = (R)kErr[0] * kk[0][q];
+            R e = (R)tab_e<M>(0) * kk[0][q];
 #pragma unroll
-            for (int l = 2; l < 7; ++l) e += (R)kErr[l] * kk[l][q];
+            for (int l = 1; l < 7; ++l)
+                if (tab_e<M>(l) != 0.0) e += (R)tab_e<M>(l) * kk[l][q];
             // Scaled error e_i / (atol + rtol max(|x_i|, |x_new,i|)); the ratio
             // in R, its square accumulated in FP64.
             const R ax = O::abs(x[q]), an = O::abs(y[q]);
@@ -605,19 +649,38 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
             const double t_new = clipped ? t_stop : t + hs;
             while (kout < a.n_t && a.t_out[kout] <= t_new) {
                 const R th = (R)((a.t_out[kout] - t) / hs);
-                const R th1 = (R)1 - th;
+                if constexpr (M == kTsit5) {
+                    R bt[7];
 #pragma unroll
-                for (int q = 0; q < GPL; ++q) {
-                    if (g_id[q] >= 0) {
-                        const R ydiff = y[q] - x[q];
-                        const R bspl = hR * kk[0][q] - ydiff;
-                        const R c4 = ydiff - hR * kk[6][q] - bspl;
-                        R c5 = (R)kDense[0] * kk[0][q];
+                    for (int l = 0; l < 7; ++l)
+                        bt[l] = th * ((R)kTsDense[l][0] +
+                                      th * ((R)kTsDense[l][1] + th * ((R)kTsDense[l][2] + th * (R)kTsDense[l][3])));
 #pragma unroll
-                        for (int l = 2; l < 7; ++l) c5 += (R)kDense[l] * kk[l][q];
-                        c5 *= hR;
-                        xo[(int64_t)kout * N + g_id[q]] =
-                            x[q] + th * (ydiff + th1 * (bspl + th * (c4 + th1 * c5)));
+                    for (int q = 0; q < GPL; ++q) {
+                        if (g_id[q] >= 0) {
+                            R acc = bt[0] * kk[0][q];
+#pragma unroll
+                            for (int l = 1; l < 7; ++l) acc += bt[l] * kk[l][q];
+                            xo[(int64_t)kout * N + g_id[q]] = x[q] + hR * acc;
+                        }
+                    }
+                } else {
+                    // Continuous extension of order 4 (Hairer, Norsett,
+                    // Wanner I, Sec. II.6).
+                    const R th1 = (R)1 - th;
+#pragma unroll
+                    for (int q = 0; q < GPL; ++q) {
+                        if (g_id[q] >= 0) {
+                            const R ydiff = y[q] - x[q];
+                            const R bspl = hR * kk[0][q] - ydiff;
+                            const R c4 = ydiff - hR * kk[6][q] - bspl;
+                            R c5 = (R)kDense[0] * kk[0][q];
+#pragma unroll
+                            for (int l = 2; l < 7; ++l) c5 += (R)kDense[l] * kk[l][q];
+                            c5 *= hR;
+                            xo[(int64_t)kout * N + g_id[q]] =
+                                x[q] + th * (ydiff + th1 * (bspl + th * (c4 + th1 * c5)));
+                        }
                     }
                 }
                 ++kout;

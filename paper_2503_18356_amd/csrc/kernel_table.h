@@ -13,6 +13,7 @@ struct KernelEntry {
     int epl, gpl;   // compiled slot budgets
     bool bounded;   // serving step-batch variant
     const void* fn; // __global__ function
+    int method;     // RAC_DP5 / RAC_TSIT5
 };
 
 // Each instantiation unit appends its entries.
@@ -21,7 +22,12 @@ int kernels_f32_ts(const KernelEntry** out);
 int kernels_f64_ss(const KernelEntry** out);
 int kernels_f64_ts(const KernelEntry** out);
 int kernels_f32_serve(const KernelEntry** out);
+int kernels_f32_ss_tsit5(const KernelEntry** out);
+int kernels_f32_ts_tsit5(const KernelEntry** out);
+int kernels_f64_ss_tsit5(const KernelEntry** out);
+int kernels_f64_ts_tsit5(const KernelEntry** out);
 
-const KernelEntry* find_kernel(int precision, bool ts, int epl, int gpl, bool bounded = false);
+const KernelEntry* find_kernel(int precision, bool ts, int epl, int gpl, bool bounded = false,
+                               int method = RAC_DP5);
 
 }  // namespace rac

@@ -1,0 +1,23 @@
+// Instantiations of the Tsitouras 5(4) kernel: double state, time-series mode.
+#include "dp5_kernel.h"
+#include "kernel_table.h"
+#include "rac.h"
+
+namespace rac {
+
+#define RAC_K(E, G)                                                                          \
+    {RAC_FP64, true, E, G, false,                                                            \
+     reinterpret_cast<const void*>(&dp5_kernel<double, E, G, true, false, kTsit5>), RAC_TSIT5}
+
+static const KernelEntry kTable[] = {
+    RAC_K(4, 1), RAC_K(4, 2), RAC_K(4, 3), RAC_K(4, 4), RAC_K(4, 6), RAC_K(8, 1), RAC_K(8, 2),
+    RAC_K(8, 3), RAC_K(8, 4), RAC_K(12, 1), RAC_K(12, 2), RAC_K(12, 3), RAC_K(16, 1),
+    RAC_K(16, 2),
+};
+
+int kernels_f64_ts_tsit5(const KernelEntry** out) {
+    *out = kTable;
+    return (int)(sizeof(kTable) / sizeof(kTable[0]));
+}
+
+}  // namespace rac

@@ -79,6 +79,8 @@ rac_status rac_server_create(const rac_solver_opts* opts, int32_t epl, int32_t g
     if (!(opts->t_end > opts->t0)) return fail(RAC_EINVAL, "rac_server_create: t_end <= t0");
     if (opts->precision != RAC_FP32)
         return fail(RAC_EUNSUPPORTED, "rac_server_create: serving step batches are compiled for RAC_FP32");
+    if (opts->method != RAC_DP5)
+        return fail(RAC_EUNSUPPORTED, "rac_server_create: serving step batches are compiled for RAC_DP5");
     if (opts->lanes_per_traj < 1) return fail(RAC_EINVAL, "rac_server_create: lanes_per_traj must be set");
     if (max_requests < 1 || batch_steps < 1)
         return fail(RAC_EINVAL, "rac_server_create: need max_requests >= 1 and batch_steps >= 1");

@@ -22,10 +22,12 @@ namespace rac {
             return fail(RAC_EDEVICE, std::string(what) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-const KernelEntry* find_kernel(int precision, bool ts, int epl, int gpl, bool bounded) {
+const KernelEntry* find_kernel(int precision, bool ts, int epl, int gpl, bool bounded, int method) {
     static std::vector<KernelEntry> all = [] {
         std::vector<KernelEntry> v;
-        for (auto fn : {kernels_f32_ss, kernels_f32_ts, kernels_f64_ss, kernels_f64_ts, kernels_f32_serve}) {
+        for (auto fn : {kernels_f32_ss, kernels_f32_ts, kernels_f64_ss, kernels_f64_ts, kernels_f32_serve,
+                        kernels_f32_ss_tsit5, kernels_f32_ts_tsit5, kernels_f64_ss_tsit5,
+                        kernels_f64_ts_tsit5}) {
             const KernelEntry* t = nullptr;
             int n = fn(&t);
             v.insert(v.end(), t, t + n);
@@ -33,7 +35,8 @@ const KernelEntry* find_kernel(int precision, bool ts, int epl, int gpl, bool bo
         return v;
     }();
     for (const KernelEntry& k : all)
-        if (k.precision == precision && k.ts == ts && k.epl == epl && k.gpl == gpl && k.bounded == bounded)
+        if (k.precision == precision && k.ts == ts && k.epl == epl && k.gpl == gpl && k.bounded == bounded &&
+            k.method == method)
             return &k;
     return nullptr;
 }
@@ -127,6 +130,8 @@ rac_status check_opts(const rac_solver_opts* o, const char* who) {
         (o->lanes_per_traj & (o->lanes_per_traj - 1)))
         return fail(RAC_EINVAL, w + ": lanes_per_traj must be 0 or a power of two <= 64");
     if (o->refill_min < 0) return fail(RAC_EINVAL, w + ": refill_min < 0");
+    if (o->method != RAC_DP5 && o->method != RAC_TSIT5)
+        return fail(RAC_EINVAL, w + ": method must be RAC_DP5 or RAC_TSIT5");
     return RAC_OK;
 }
 
@@ -227,7 +232,8 @@ rac_status launch_group(const std::vector<Job>& jobs, int lpt, const rac_solver_
     }
     if (total == 0) return RAC_OK;
     const Shape shape = pick_shape(std::max(epl, 1), gpl, o->precision);
-    const KernelEntry* ke = shape.epl ? find_kernel(o->precision, ts, shape.epl, shape.gpl) : nullptr;
+    const KernelEntry* ke =
+        shape.epl ? find_kernel(o->precision, ts, shape.epl, shape.gpl, false, o->method) : nullptr;
     if (!ke) return fail(RAC_EUNSUPPORTED, "no compiled kernel for this network size and lane count");
 
     int dev = 0, n_cu = 0;
@@ -345,6 +351,7 @@ void rac_default_opts(rac_solver_opts* o, int32_t precision) {
     o->ic_absolute = 0;
     o->lanes_per_traj = 0;
     o->refill_min = 0;
+    o->method = RAC_DP5;
 }
 
 rac_status rac_steady_states(const rac_topology* topo, const rac_params_view* dev_params,

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "librac.so")
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
 CONVERGED, T_END, MAX_STEPS, STEP_UNDERFLOW, NONFINITE = range(5)
 FP32, FP64 = 0, 1
+DP5, TSIT5 = 0, 1  # rac_method
 STATUS_NAMES = ["CONVERGED", "T_END", "MAX_STEPS", "STEP_UNDERFLOW", "NONFINITE"]
 
 
@@ -50,7 +51,7 @@ class _Opts(C.Structure):
                 ("h0", C.c_double), ("max_steps", C.c_int64), ("precision", C.c_int32),
                 ("activation_divides_by_lambda", C.c_int32), ("stop_at_steady", C.c_int32),
                 ("ic_absolute", C.c_int32), ("lanes_per_traj", C.c_int32),
-                ("refill_min", C.c_int32)]
+                ("refill_min", C.c_int32), ("method", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -296,6 +297,7 @@ class Opts:
     ic_absolute: int = 0
     lanes_per_traj: int = 0
     refill_min: int = 0
+    method: int = 0  # DP5 or TSIT5
 
     def c(self) -> _Opts:
         o = _Opts()

@@ -133,6 +133,7 @@ def _fake_result():
 @pytest.mark.parametrize("bad", [
     dict(t_end=0.0), dict(rtol=0.0, atol=0.0), dict(rtol=-1.0), dict(max_steps=0),
     dict(precision=7), dict(lanes_per_traj=3), dict(ss_atol=-1.0), dict(t0=float("nan")),
+    dict(method=2), dict(method=-1),
 ])
 def test_steady_states_rejects_bad_options_before_enqueue(bad):
     t = rp.Topology.from_inputs(inputs.toggle_switch())
@@ -158,3 +159,13 @@ def test_lane_choices():
     assert big.auto_lanes() >= 8
     assert not big.lanes_supported(1)
     assert not ts.lanes_supported(3)
+
+
+def test_default_options_and_server_method_check():
+    o = rp.Opts().c()
+    assert o.method == rp.DP5 and o.rtol == 1e-6 and o.atol == 1e-9
+    # Serving step batches are compiled for DP5 only: rejected before any
+    # device call.
+    with pytest.raises(rp.RacError) as e:
+        rp.StepServer(rp.Opts(method=rp.TSIT5), 4, 8, 3)
+    assert e.value.code == rp.EUNSUPPORTED

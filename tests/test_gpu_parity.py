@@ -55,11 +55,12 @@ class Case:
                            ss_atol=opts.ss_atol, ss_rtol=ss_rtol, h0=opts.h0,
                            max_steps=opts.max_steps,
                            divide_act_by_lambda=opts.activation_divides_by_lambda,
-                           stop_at_steady=opts.stop_at_steady, ic_absolute=opts.ic_absolute)
+                           stop_at_steady=opts.stop_at_steady, ic_absolute=opts.ic_absolute,
+                           method=opts.method)
 
     def check(self, opts, sample=None, seed=0, label=""):
         say(f"[gpu] {label} {self.topo.name} P={self.hp.n_sets} n_ic={self.n_ic} "
-            f"prec={opts.precision} lanes={opts.lanes_per_traj}")
+            f"prec={opts.precision} lanes={opts.lanes_per_traj} method={opts.method}")
         out = self.gpu(opts)
         st = out.status.cpu().numpy()
         if sample is None or sample >= self.n_traj:
