@@ -240,6 +240,19 @@ def bench_er10(args, torch, rp, flops, inputs):
                                                        + out64.n_rej.cpu().numpy()).mean())}
         rec["speedup_fp32_vs_fp64"] = value / v64
         del out64
+    if not args.no_plain:
+        # The same workload with the paper's own solver (Tsitouras 5(4)).
+        o_ts = rp.Opts(precision=rp.FP32, method=rp.TSIT5, lanes_per_traj=args.lanes,
+                       refill_min=args.refill_min)
+        step_ts = lambda: rp.steady_states(T, dp, o_ts, out=out, stream=stream)
+        step_ts()
+        w_ts, lat_ts = timed(step_ts, max(1, args.steps), stream, torch)
+        rec["tsit5_fp32"] = {
+            "value": solved(rp, out.status) * max(1, args.steps) / w_ts, "unit": "solves/s",
+            "kernel_ms": float(lat_ts.mean()),
+            "steps_per_solve": float((out.n_acc.cpu().numpy().astype(np.int64)
+                                      + out.n_rej.cpu().numpy()).mean()),
+            "what": "FP32 chosen form with the Tsitouras 5(4) pair instead of Dormand-Prince"}
     if not args.no_serve:
         rec["serving"] = serving_run(args.serve_requests, args.serve_warmup, args.serve_rate)
         rec["latency_ms"] = {"p50": rec["serving"]["p50_ms"], "p99": rec["serving"]["p99_ms"],
