@@ -294,6 +294,68 @@ rac_status rac_server_done_counts(rac_server* s, int32_t first, int32_t count, i
 rac_status rac_server_info(const rac_server* s, int32_t* n_requests, int64_t* total_trajectories,
                            int32_t* grid_waves, int64_t* slot_bytes);
 
+/* ------------------------------------------------------------------------ */
+/* Post-processing of results (the analysis functions of Sec. 2.1.4 and their */
+/* use in Sec. 3.1), on the device.                                           */
+/* ------------------------------------------------------------------------ */
+/* A row is one state vector of N genes: row r = p * n_ic + c of a steady-state
+ * result, or (p * n_ic + c) * n_t + j of a time series.  All arrays are
+ * caller-owned device memory; every call is stream-ordered and asynchronous
+ * and returns argument errors before enqueueing anything. */
+#define RAC_NO_STATE 0xFFFFFFFFFFFFFFFFull /* state code of an excluded row */
+
+/* G/k normalisation: y[r][i] = (x[r][i] * k_i) / G_i of the row's parameter
+ * set, each operation rounded to FP32, so that 1 is the gene's maximal level
+ * (Sec. 2.1.4).  x and y are [P * n_ic * n_t][N] f32 (y may be x).
+ * EINVAL: NULL pointers, n_ic < 1, n_t < 1. */
+rac_status rac_normalize(const rac_topology* topo, const rac_params_view* dev_params, int32_t n_ic,
+                         int32_t n_t, const float* dev_x, float* dev_y, void* hip_stream);
+
+/* Level thresholds from the global distribution of normalised values
+ * (Sec. 2.1.4; the paper does not state the method, this is the library's
+ * reading).  Bins: b = min(floor(clamp(y, 0, 1) * n_bins), n_bins - 1) in FP32
+ * (NaN counts as 0); dev_hist[n_bins] (u64) receives the counts over all
+ * genes of the rows whose dev_status is RAC_CONVERGED (all rows if
+ * dev_status is NULL).  dev_thresholds[n_levels - 1] receives the bin indices
+ * 0 < t_1 < ... < t_{L-1} < n_bins maximising sum_k S_k^2 / W_k over the
+ * classes [t_k, t_{k+1}) (W = count, S = sum of bin indices; Otsu's
+ * between-class variance up to constants), evaluated in FP64 in class order;
+ * the lexicographically first maximum wins.  EINVAL: n_bins outside
+ * [2, 1024], n_levels outside [2, 4], NULL pointers.  EUNSUPPORTED: four
+ * levels with n_bins > 256. */
+rac_status rac_level_thresholds(const float* dev_y, int64_t n_rows, int32_t n_genes,
+                                const int8_t* dev_status, int32_t n_bins, int32_t n_levels,
+                                uint64_t* dev_hist, int32_t* dev_thresholds, void* hip_stream);
+
+/* Levels and state codes: level = number of thresholds <= the value's bin;
+ * dev_levels[n_rows][N] (u8, 255 for excluded rows; may be NULL) and
+ * dev_codes[n_rows] = sum_i level_i * n_levels^(N-1-i), gene 0 most
+ * significant (the concatenated levels of Sec. 3.1; RAC_NO_STATE for rows
+ * whose status is not RAC_CONVERGED; may be NULL).  EUNSUPPORTED when codes
+ * are asked for and n_levels^N exceeds 64 bits. */
+rac_status rac_discretize(const float* dev_y, int64_t n_rows, int32_t n_genes,
+                          const int8_t* dev_status, int32_t n_bins, int32_t n_levels,
+                          const int32_t* dev_thresholds, uint8_t* dev_levels, uint64_t* dev_codes,
+                          void* hip_stream);
+
+/* Multistability of each parameter set (Sec. 3.1): the number of distinct
+ * states over its n_ic initial conditions (RAC_NO_STATE rows excluded) in
+ * dev_n_states[n_sets] (i32), and those states in ascending order in
+ * dev_states[n_sets][n_ic] (u64), padded with RAC_NO_STATE.  Input codes are
+ * [n_sets][n_ic].  EUNSUPPORTED: n_ic > 4096. */
+rac_status rac_multistability(const uint64_t* dev_codes, int64_t n_sets, int32_t n_ic,
+                              int32_t* dev_n_states, uint64_t* dev_states, void* hip_stream);
+
+/* State frequencies over all rows (Sec. 3.1): the distinct codes in ascending
+ * order in dev_keys[capacity] with their counts in dev_counts[capacity]
+ * (unused entries RAC_NO_STATE / 0), and their number in *dev_n_unique, or -1
+ * when more than `capacity` distinct states occur (a hash table of that many
+ * slots; the library allocates it stream-ordered).  EINVAL: capacity not a
+ * power of two in [2, 2^30], NULL pointers. */
+rac_status rac_state_counts(const uint64_t* dev_codes, int64_t n_rows, int64_t capacity,
+                            uint64_t* dev_keys, int64_t* dev_counts, int64_t* dev_n_unique,
+                            void* hip_stream);
+
 /* The lanes-per-trajectory choice the library would make for a network
  * (0 if none fits), and whether a given choice fits the compiled kernels. */
 int32_t rac_auto_lanes(const rac_topology* topo, int32_t precision);

@@ -10,7 +10,7 @@ frequencies).  The paper does not give the levels algorithm; this module
 implements the reading used throughout this repository:
 
 - y = (x * k) / G, each operation rounded to FP32;
-- bin b = min(floor(y * B), B - 1) after clamping y to [0, 1], FP32;
+- bin b = min(floor(y * B), B - 1) after clamping y to [0, 1] (NaN to 0), FP32;
 - a histogram over all genes and all included rows (rows whose status is
   CONVERGED when statuses are given);
 - L levels from the thresholds 0 < t_1 < ... < t_{L-1} < B (bin indices) that
@@ -47,7 +47,8 @@ def normalize(x, G, k, n_ic: int, n_t: int = 1):
 
 def bins_of(y, n_bins: int):
     y = np.asarray(y, np.float32)
-    yc = np.minimum(np.maximum(y, np.float32(0)), np.float32(1))
+    # fmax/fmin ignore NaN, so NaN counts as 0.
+    yc = np.fmin(np.fmax(y, np.float32(0)), np.float32(1))
     b = np.floor(yc * np.float32(n_bins)).astype(np.int64)
     return np.minimum(b, n_bins - 1)
 
@@ -97,14 +98,14 @@ def levels(y, n_bins: int, thr, status=None):
 
 def codes(lv, n_levels: int, status=None):
     lv = np.asarray(lv)
-    out = np.zeros(lv.shape[0], np.uint64)
+    out = np.full(lv.shape[0], NO_STATE, np.uint64)
     for r in range(lv.shape[0]):
+        if status is not None and status[r] != CONVERGED:
+            continue
         c = 0
         for i in range(lv.shape[1]):
             c = c * n_levels + int(lv[r, i])
         out[r] = np.uint64(c)
-    if status is not None:
-        out[np.asarray(status) != CONVERGED] = NO_STATE
     return out
 
 

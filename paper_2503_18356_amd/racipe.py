@@ -118,6 +118,16 @@ def lib():
         L.rac_server_done_counts.restype = C.c_int
         L.rac_server_info.argtypes = [vp, vp, vp, vp, vp]
         L.rac_server_info.restype = C.c_int
+        L.rac_normalize.argtypes = [vp, C.POINTER(_ParamsView), i32, i32, vp, vp, vp]
+        L.rac_normalize.restype = C.c_int
+        L.rac_level_thresholds.argtypes = [vp, i64, i32, vp, i32, i32, vp, vp, vp]
+        L.rac_level_thresholds.restype = C.c_int
+        L.rac_discretize.argtypes = [vp, i64, i32, vp, i32, i32, vp, vp, vp, vp]
+        L.rac_discretize.restype = C.c_int
+        L.rac_multistability.argtypes = [vp, i64, i32, vp, vp, vp]
+        L.rac_multistability.restype = C.c_int
+        L.rac_state_counts.argtypes = [vp, i64, i64, vp, vp, vp, vp]
+        L.rac_state_counts.restype = C.c_int
         _lib = L
     return _lib
 
@@ -431,3 +441,87 @@ class StepServer:
         if h and _lib is not None:
             _lib.rac_server_destroy(h)
             self._h = None
+
+
+# --------------------------------------------------------------------------
+# Post-processing (rac_normalize ... rac_state_counts).  State codes travel
+# as int64 tensors holding the u64 bits; RAC_NO_STATE reads as -1.
+# --------------------------------------------------------------------------
+NO_STATE = -1
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def normalize(topo: Topology, params: DeviceParams, x, n_t: int = 1, out=None, stream=None):
+    """G/k-normalised copy of a float32 result x ([P*n_ic*n_t][N] or any shape
+    with that many elements)."""
+    import torch
+    assert x.dtype == torch.float32 and x.is_contiguous()
+    y = out if out is not None else torch.empty_like(x)
+    v = params.view()
+    _check(lib().rac_normalize(topo.handle, C.byref(v), params.n_ic, n_t, x.data_ptr(), y.data_ptr(),
+                               _stream_ptr(stream)))
+    return y
+
+
+def level_thresholds(y, n_genes: int, status=None, n_bins: int = 64, n_levels: int = 2, stream=None):
+    """(hist int64[n_bins], thresholds int32[n_levels-1]) on the device."""
+    import torch
+    n_rows = y.numel() // n_genes
+    hist = torch.empty(n_bins, dtype=torch.int64, device=y.device)
+    thr = torch.empty(n_levels - 1, dtype=torch.int32, device=y.device)
+    _check(lib().rac_level_thresholds(y.data_ptr(), n_rows, n_genes, _ptr(status), n_bins, n_levels,
+                                      hist.data_ptr(), thr.data_ptr(), _stream_ptr(stream)))
+    return hist, thr
+
+
+def discretize(y, n_genes: int, thresholds, status=None, n_bins: int = 64, n_levels: int = 2,
+               want_levels: bool = True, want_codes: bool = True, stream=None):
+    """(levels uint8[rows][N] or None, codes int64[rows] or None)."""
+    import torch
+    n_rows = y.numel() // n_genes
+    lv = torch.empty((n_rows, n_genes), dtype=torch.uint8, device=y.device) if want_levels else None
+    cd = torch.empty(n_rows, dtype=torch.int64, device=y.device) if want_codes else None
+    _check(lib().rac_discretize(y.data_ptr(), n_rows, n_genes, _ptr(status), n_bins, n_levels,
+                                thresholds.data_ptr(), _ptr(lv), _ptr(cd), _stream_ptr(stream)))
+    return lv, cd
+
+
+def multistability(codes, n_sets: int, n_ic: int, stream=None):
+    """(n_states int32[n_sets], states int64[n_sets][n_ic])."""
+    import torch
+    n = torch.empty(n_sets, dtype=torch.int32, device=codes.device)
+    st = torch.empty((n_sets, n_ic), dtype=torch.int64, device=codes.device)
+    _check(lib().rac_multistability(codes.data_ptr(), n_sets, n_ic, n.data_ptr(), st.data_ptr(),
+                                    _stream_ptr(stream)))
+    return n, st
+
+
+def state_counts(codes, capacity: int = 1 << 16, stream=None):
+    """(keys int64[capacity], counts int64[capacity], n_unique int64[1]) on the
+    device; the first n_unique entries are the distinct states in ascending
+    unsigned order."""
+    import torch
+    keys = torch.empty(capacity, dtype=torch.int64, device=codes.device)
+    counts = torch.empty(capacity, dtype=torch.int64, device=codes.device)
+    nu = torch.empty(1, dtype=torch.int64, device=codes.device)
+    _check(lib().rac_state_counts(codes.data_ptr(), codes.numel(), capacity, keys.data_ptr(),
+                                  counts.data_ptr(), nu.data_ptr(), _stream_ptr(stream)))
+    return keys, counts, nu
+
+
+def analyse_steady_states(topo: Topology, params: DeviceParams, result: Result, n_bins: int = 64,
+                          n_levels: int = 2, capacity: int = 1 << 16, stream=None) -> dict:
+    """The whole chain on a steady-state result, all on the device: normalised
+    states, histogram and thresholds, levels and state codes, multistability
+    per parameter set and global state frequencies."""
+    N = topo.n_genes
+    y = normalize(topo, params, result.x, 1, stream=stream)
+    hist, thr = level_thresholds(y, N, result.status, n_bins, n_levels, stream=stream)
+    lv, cd = discretize(y, N, thr, result.status, n_bins, n_levels, stream=stream)
+    n_states, states = multistability(cd, params.n_sets, params.n_ic, stream=stream)
+    keys, counts, nu = state_counts(cd, capacity, stream=stream)
+    return dict(y=y, hist=hist, thresholds=thr, levels=lv, codes=cd, n_states=n_states,
+                states=states, keys=keys, counts=counts, n_unique=nu)

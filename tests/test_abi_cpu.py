@@ -169,3 +169,28 @@ def test_default_options_and_server_method_check():
     with pytest.raises(rp.RacError) as e:
         rp.StepServer(rp.Opts(method=rp.TSIT5), 4, 8, 3)
     assert e.value.code == rp.EUNSUPPORTED
+
+
+def test_postprocessing_rejects_bad_arguments_before_enqueue():
+    L = rp.lib()
+    s = None  # never reached: the checks fail first
+    fake = 0x1000
+    # n_bins / n_levels outside their ranges.
+    for bins, levels in ((1, 2), (2000, 2), (64, 1), (64, 5), (3, 4)):
+        assert L.rac_level_thresholds(fake, 10, 2, None, bins, levels, fake, fake, s) == rp.EINVAL
+    assert L.rac_level_thresholds(fake, 10, 2, None, 512, 4, fake, fake, s) == rp.EUNSUPPORTED
+    assert L.rac_level_thresholds(fake, 10, 2, None, 64, 2, None, fake, s) == rp.EINVAL
+    # Codes that do not fit 64 bits: 2^64 states of 64 binary genes.
+    assert L.rac_discretize(fake, 10, 64, None, 64, 2, fake, None, fake, s) == rp.EUNSUPPORTED
+    assert L.rac_discretize(fake, 10, 40, None, 64, 4, fake, None, fake, s) == rp.EUNSUPPORTED
+    assert L.rac_discretize(fake, 10, 4, None, 64, 2, fake, None, None, s) == rp.EINVAL
+    # Per-set state lists are bounded; capacities are powers of two.
+    assert L.rac_multistability(fake, 10, 5000, fake, fake, s) == rp.EUNSUPPORTED
+    assert L.rac_multistability(fake, 10, 0, fake, fake, s) == rp.EINVAL
+    for cap in (0, 1, 3, 1000, 1 << 31):
+        assert L.rac_state_counts(fake, 10, cap, fake, fake, fake, s) == rp.EINVAL
+    t = rp.Topology.from_inputs(inputs.toggle_switch())
+    p = _fake_params(2, 2, 4, 2)
+    v = p.view()
+    assert L.rac_normalize(t.handle, C.byref(v), 0, 1, fake, fake, s) == rp.EINVAL
+    assert L.rac_normalize(t.handle, C.byref(v), 2, 1, None, fake, s) == rp.EINVAL
