@@ -241,6 +241,19 @@ def bench_er10(args, torch, rp, flops, inputs):
         rec["speedup_fp32_vs_fp64"] = value / v64
         del out64
     if not args.no_plain:
+        # Post-processing of the 10^6 steady states on the device (normalise,
+        # levels, codes, multistability, state counts): HBM-bound.
+        post = lambda: rp.analyse_steady_states(T, dp, out, 64, 2, 1 << 16, stream=stream)
+        post()
+        w_pp, lat_pp = timed(post, 5, stream, torch)
+        nb = flops.postproc_bytes(T.n_genes, args.n_sets, args.n_ic, n_bins=64, capacity=1 << 16)
+        rec["postproc"] = {
+            "ms": float(lat_pp.mean()), "algorithmic_bytes": nb,
+            "achieved_GBps": nb / (lat_pp.mean() * 1e-3) / 1e9, "peak_GBps": PEAK_HBM / 1e9,
+            "frac": nb / (lat_pp.mean() * 1e-3) / PEAK_HBM,
+            "what": "normalise + histogram/thresholds + levels/codes + multistability + state counts "
+                    "of the 1e6 x 10 steady states, 64 bins, 2 levels"}
+    if not args.no_plain:
         # The same workload with the paper's own solver (Tsitouras 5(4)).
         o_ts = rp.Opts(precision=rp.FP32, method=rp.TSIT5, lanes_per_traj=args.lanes,
                        refill_min=args.refill_min)

@@ -39,7 +39,9 @@ class _Ranges(C.Structure):
                 ("k_max", C.c_double), ("lam_act_min", C.c_double), ("lam_act_max", C.c_double),
                 ("lam_inh_min", C.c_double), ("lam_inh_max", C.c_double),
                 ("n_min", C.c_int32), ("n_max", C.c_int32), ("t_lo", C.c_double),
-                ("t_hi", C.c_double), ("t_median", C.c_double)]
+                ("t_hi", C.c_double), ("t_median", C.c_double), ("method", C.c_int32),
+                ("threshold_rule", C.c_int32), ("hf_samples", C.c_int32),
+                ("hf_act_over_lambda", C.c_int32), ("lhs_total", C.c_int64)]
 
 
 class _Opts(C.Structure):
@@ -70,9 +72,17 @@ def load(path: str):
     L.orc_default_ranges.argtypes = [C.POINTER(_Ranges)]
     L.orc_gk_median.argtypes = [C.POINTER(_Ranges)]
     L.orc_gk_median.restype = C.c_double
-    L.orc_sample.argtypes = [C.c_int, C.c_int, vp, C.POINTER(_Ranges), u64, i64, i64, i32,
+    L.orc_sample.argtypes = [C.c_int, C.c_int, vp, vp, vp, C.POINTER(_Ranges), u64, i64, i64, i32,
                              vp, vp, vp, vp, vp, vp]
     L.orc_sample.restype = C.c_int
+    L.orc_hf_median.argtypes = [C.POINTER(_Ranges), i32, i32]
+    L.orc_hf_median.restype = C.c_double
+    L.orc_sobol_u32.argtypes = [i64, i32, C.POINTER(C.c_uint32)]
+    L.orc_sobol_u32.restype = C.c_int
+    L.orc_primitive_count.argtypes = [i32]
+    L.orc_primitive_count.restype = C.c_int
+    L.orc_lhs_perm.argtypes = [u64, i32, i32, i64, i64]
+    L.orc_lhs_perm.restype = i64
     L.orc_default_opts.argtypes = [C.POINTER(_Opts)]
     L.orc_rhs.argtypes = [C.POINTER(_Problem), i64, i32, vp, vp]
     L.orc_steady_states.argtypes = [C.POINTER(_Problem), C.POINTER(_Opts), vp, i64, i32,
@@ -152,6 +162,11 @@ class Ranges:
     t_lo: float = 0.02
     t_hi: float = 1.98
     t_median: float = 0.0
+    method: int = 0           # UNIFORM, SOBOL, LHS
+    threshold_rule: int = 0   # PRIOR_MEDIAN, HALF_FUNCTIONAL
+    hf_samples: int = 65536
+    hf_act_over_lambda: int = 1
+    lhs_total: int = 0
 
     def c(self) -> _Ranges:
         return _Ranges(*[getattr(self, f[0]) for f in _Ranges._fields_])
@@ -183,7 +198,8 @@ def sample(net: Network, seed: int, n_sets: int, n_ic: int, set_begin: int = 0,
     T = np.zeros((E, P), np.float32); lam = np.zeros((E, P), np.float32)
     n = np.zeros((E, P), np.uint8); ic = np.zeros((n_ic, N), np.float32)
     rr = (ranges or Ranges()).c()
-    rc = lib().orc_sample(N, E, _ptr(net.sign), C.byref(rr), C.c_uint64(seed & (2**64 - 1)),
+    rc = lib().orc_sample(N, E, _ptr(net.src), _ptr(net.dst), _ptr(net.sign), C.byref(rr),
+                          C.c_uint64(seed & (2**64 - 1)),
                           set_begin, P, n_ic, _ptr(G), _ptr(k), _ptr(T), _ptr(lam), _ptr(n), _ptr(ic))
     if rc != 0:
         raise ValueError("orc_sample failed")
@@ -191,6 +207,28 @@ def sample(net: Network, seed: int, n_sets: int, n_ic: int, set_begin: int = 0,
 
 
 DP5, TSIT5 = 0, 1
+UNIFORM, SOBOL, LHS = 0, 1, 2
+PRIOR_MEDIAN, HALF_FUNCTIONAL = 0, 1
+
+
+def hf_median(n_act: int, n_inh: int, ranges: "Ranges | None" = None) -> float:
+    rr = (ranges or Ranges()).c()
+    return lib().orc_hf_median(C.byref(rr), n_act, n_inh)
+
+
+def sobol_u32(i: int, q: int) -> int:
+    v = C.c_uint32(0)
+    if lib().orc_sobol_u32(i, q, C.byref(v)) != 0:
+        raise ValueError("Sobol index or dimension out of range")
+    return v.value
+
+
+def primitive_count(s: int) -> int:
+    return lib().orc_primitive_count(s)
+
+
+def lhs_perm(seed: int, domain: int, q: int, n: int, i: int) -> int:
+    return lib().orc_lhs_perm(C.c_uint64(seed & (2**64 - 1)), domain, q, n, i)
 
 
 def tableau(method: int):

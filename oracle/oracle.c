@@ -96,6 +96,11 @@ void orc_default_ranges(orc_ranges* r) {
     /* Half-functional window: 0.02 .. 1.98 times the median. */
     r->t_lo = 0.02; r->t_hi = 1.98;
     r->t_median = 0.0;
+    r->method = ORC_UNIFORM;
+    r->threshold_rule = ORC_T_PRIOR_MEDIAN;
+    r->hf_samples = 65536;
+    r->hf_act_over_lambda = 1;
+    r->lhs_total = 0;
 }
 
 /* CDF of G/k for independent G ~ U[a,b], k ~ U[c,d]:
@@ -136,34 +141,269 @@ double orc_gk_median(const orc_ranges* r) {
     return 0.5 * (lo + hi);
 }
 
-int orc_sample(int n_genes, int n_edges, const int8_t* sign, const orc_ranges* r, uint64_t seed,
-               int64_t set_begin, int64_t n_sets, int32_t n_ic, float* G, float* k, float* T,
-               float* lam, uint8_t* n, float* ic) {
+/* ------------------------------------------------------------------------ */
+/* Sobol' sequence: primitive polynomials over GF(2) by increasing degree    */
+/* (then value); dimension q >= 1 uses the (q-1)-th.  Initial direction      */
+/* numbers m_1..m_s are odd and below 2^k, drawn once from Philox with a     */
+/* fixed key; later ones follow Bratley and Fox's recurrence.  Points are    */
+/* generated directly from the binary digits of the index.                   */
+/* ------------------------------------------------------------------------ */
+#define ORC_SOBOL_MAX_DEG 18
+#define ORC_SOBOL_MAX_DIM 4096
+
+static uint64_t orc_gf2_mulmod(uint64_t a, uint64_t b, uint64_t poly, int s) {
+    uint64_t r = 0;
+    while (b) {
+        if (b & 1) r ^= a;
+        b >>= 1;
+        a <<= 1;
+        if (a >> s & 1) a ^= poly;
+    }
+    return r;
+}
+
+static uint64_t orc_gf2_xpow(uint64_t e, uint64_t poly, int s) {
+    uint64_t result = 1, base = 2 % (1ull << s);
+    if (s == 1) base = 1; /* x = 1 mod (x + 1) */
+    while (e) {
+        if (e & 1) result = orc_gf2_mulmod(result, base, poly, s);
+        base = orc_gf2_mulmod(base, base, poly, s);
+        e >>= 1;
+    }
+    return result;
+}
+
+/* Primitive iff x has multiplicative order 2^s - 1 modulo the polynomial. */
+static int orc_is_primitive(uint64_t poly, int s) {
+    uint64_t order = (1ull << s) - 1;
+    if (orc_gf2_xpow(order, poly, s) != 1) return 0;
+    uint64_t m = order;
+    for (uint64_t f = 2; f * f <= m; ++f) {
+        if (m % f) continue;
+        while (m % f == 0) m /= f;
+        if (orc_gf2_xpow(order / f, poly, s) == 1) return 0;
+    }
+    if (m > 1 && m != order && orc_gf2_xpow(order / m, poly, s) == 1) return 0;
+    return 1;
+}
+
+static uint32_t orc_sobol_v[ORC_SOBOL_MAX_DIM][32];
+static int orc_sobol_ready = 0;
+static int orc_prim_count[ORC_SOBOL_MAX_DEG + 1];
+static pthread_once_t orc_sobol_once = PTHREAD_ONCE_INIT;
+
+static void orc_sobol_init(void) {
+    for (int b = 0; b < 32; ++b) orc_sobol_v[0][b] = 1u << (31 - b);
+    int q = 1;
+    for (int s = 1; s <= ORC_SOBOL_MAX_DEG; ++s) {
+        for (uint64_t poly = (1ull << s) | 1; poly < (2ull << s); poly += 2) {
+            if (!orc_is_primitive(poly, s)) continue;
+            orc_prim_count[s]++;
+            if (q >= ORC_SOBOL_MAX_DIM) continue;
+            uint64_t m[33];
+            for (int k = 1; k <= s && k <= 32; ++k) {
+                uint64_t ctr[4] = {(uint64_t)q, (uint64_t)k, 0, 0};
+                uint64_t key[2] = {0x536F626F6C2D6D6Bull, 0};
+                uint64_t out[4];
+                orc_philox4x64_10(ctr, key, out);
+                m[k] = (out[0] % (1ull << (k - 1))) * 2 + 1; /* odd, < 2^k */
+            }
+            for (int k = s + 1; k <= 32; ++k) {
+                uint64_t v = m[k - s] ^ (m[k - s] << s);
+                for (int j = 1; j < s; ++j)
+                    if (poly >> (s - j) & 1) v ^= m[k - j] << j;
+                m[k] = v;
+            }
+            for (int b = 0; b < 32; ++b) orc_sobol_v[q][b] = (uint32_t)(m[b + 1] << (31 - b));
+            ++q;
+        }
+    }
+    orc_sobol_ready = q;
+}
+
+int orc_sobol_u32(int64_t i, int32_t q, uint32_t* out) {
+    pthread_once(&orc_sobol_once, orc_sobol_init);
+    if (q < 0 || q >= orc_sobol_ready || i < 0 || i >= (1ll << 32)) return -1;
+    uint32_t x = 0;
+    for (int b = 0; b < 32; ++b)
+        if (((uint64_t)i >> b) & 1) x ^= orc_sobol_v[q][b];
+    *out = x;
+    return 0;
+}
+
+int orc_primitive_count(int32_t s) {
+    pthread_once(&orc_sobol_once, orc_sobol_init);
+    return (s >= 1 && s <= ORC_SOBOL_MAX_DEG) ? orc_prim_count[s] : -1;
+}
+
+/* Digital shift of dimension q in a domain (0 parameters, 1 initial
+ * conditions), keyed by the seed. */
+static uint32_t orc_sobol_shift(uint64_t seed, int32_t domain, int32_t q) {
+    uint64_t ctr[4] = {(uint64_t)q, 0, (uint64_t)(2 + domain), 0};
+    uint64_t key[2] = {seed, 0};
+    uint64_t out[4];
+    orc_philox4x64_10(ctr, key, out);
+    return (uint32_t)(out[0] >> 32);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Latin hypercube: in dimension q item i falls in stratum perm_q(i), with   */
+/* a uniform offset inside it.  perm_q is a keyed bijection of [0, n): an     */
+/* invertible mix of w-bit words (2^w >= n) applied until the value lands    */
+/* in [0, n) (cycle walking).                                                */
+/* ------------------------------------------------------------------------ */
+static uint64_t orc_lhs_mix(uint64_t x, const uint64_t k[4], int w) {
+    const uint64_t mask = w >= 64 ? ~0ull : ((1ull << w) - 1);
+    const int sh = w / 2 > 0 ? w / 2 : 1;
+    for (int r = 0; r < 4; ++r) {
+        x = (x ^ k[r]) & mask;
+        x = (x * 0x9E3779B97F4A7C15ull) & mask;  /* odd multiplier: bijective */
+        x ^= x >> sh;                            /* xorshift: bijective */
+    }
+    return x;
+}
+
+int64_t orc_lhs_perm(uint64_t seed, int32_t domain, int32_t q, int64_t n, int64_t i) {
+    if (n < 1 || i < 0 || i >= n) return -1;
+    int w = 1;
+    while ((1ll << w) < n) ++w;
+    uint64_t ctr[4] = {(uint64_t)q, 0, (uint64_t)(4 + domain), 0};
+    uint64_t key[2] = {seed, 0};
+    uint64_t k[4];
+    orc_philox4x64_10(ctr, key, k);
+    uint64_t x = (uint64_t)i;
+    do {
+        x = orc_lhs_mix(x, k, w);
+    } while (x >= (uint64_t)n);
+    return (int64_t)x;
+}
+
+/* The unit-cube coordinate of dimension q for item a (a parameter set or an
+ * initial condition) under the configured generator. */
+static double orc_unit(const orc_ranges* r, uint64_t seed, uint64_t a, uint64_t q, int domain,
+                       int64_t lhs_n) {
+    if (r->method == ORC_SOBOL) {
+        uint32_t v = 0;
+        orc_sobol_u32((int64_t)a, (int32_t)q, &v);
+        return (double)(v ^ orc_sobol_shift(seed, domain, (int32_t)q)) * 0x1.0p-32;
+    }
+    if (r->method == ORC_LHS) {
+        int64_t cell = orc_lhs_perm(seed, domain, (int32_t)q, lhs_n, (int64_t)a);
+        double jitter = orc_uniform(seed, a, q, (uint64_t)(6 + domain));
+        return ((double)cell + jitter) / (double)lhs_n;
+    }
+    return orc_uniform(seed, a, q, (uint64_t)domain);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Half-functional rule (Sec. 2.1.2): the threshold scale of an edge is the  */
+/* median level of its source.  For a source with n_act activating and      */
+/* n_inh inhibitory regulators that level is taken one step deep: its own    */
+/* G/k times the Hill terms of its in-edges, each regulator at an            */
+/* unregulated level G'/k' and each in-edge with prior T, n and lambda; the  */
+/* median over hf_samples Monte Carlo draws (Philox, fixed key), rounded to  */
+/* FP32.  Unregulated sources use the prior median of G/k.                   */
+/* ------------------------------------------------------------------------ */
+static double orc_shifted_hill(double B, double B0, double n, double lam);
+
+static int orc_cmp_double(const void* a, const void* b) {
+    double x = *(const double*)a, y = *(const double*)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static double orc_hf_draw(uint64_t na, uint64_t nh, uint64_t s, uint64_t d) {
+    uint64_t ctr[4] = {na, nh, s, d / 4};
+    uint64_t key[2] = {0x48616C662D66756Eull, 0};
+    uint64_t out[4];
+    orc_philox4x64_10(ctr, key, out);
+    return (double)(out[d % 4] >> 11) * 0x1.0p-53;
+}
+
+double orc_hf_median(const orc_ranges* r, int32_t n_act, int32_t n_inh) {
+    const double M0 = orc_gk_median(r);
+    if (n_act + n_inh == 0 || r->hf_samples < 1) return M0;
+    const int S = r->hf_samples;
+    double* v = (double*)malloc(sizeof(double) * (size_t)S);
+    for (int s = 0; s < S; ++s) {
+        uint64_t d = 0;
+        double G = r->g_min + (r->g_max - r->g_min) * orc_hf_draw(n_act, n_inh, s, d++);
+        double k = r->k_min + (r->k_max - r->k_min) * orc_hf_draw(n_act, n_inh, s, d++);
+        double x = G / k;
+        for (int e = 0; e < n_act + n_inh; ++e) {
+            double Gs = r->g_min + (r->g_max - r->g_min) * orc_hf_draw(n_act, n_inh, s, d++);
+            double ks = r->k_min + (r->k_max - r->k_min) * orc_hf_draw(n_act, n_inh, s, d++);
+            double T = M0 * (r->t_lo + (r->t_hi - r->t_lo) * orc_hf_draw(n_act, n_inh, s, d++));
+            int32_t span = r->n_max - r->n_min + 1;
+            int32_t off = (int32_t)floor(orc_hf_draw(n_act, n_inh, s, d++) * span);
+            if (off > span - 1) off = span - 1;
+            double u = orc_hf_draw(n_act, n_inh, s, d++);
+            double lam;
+            if (e < n_act) {
+                lam = r->lam_act_min + (r->lam_act_max - r->lam_act_min) * u;
+            } else {
+                double inv_lo = 1.0 / r->lam_inh_max, inv_hi = 1.0 / r->lam_inh_min;
+                lam = 1.0 / (inv_lo + (inv_hi - inv_lo) * u);
+            }
+            double h = orc_shifted_hill(Gs / ks, T, (double)(r->n_min + off), lam);
+            if (e < n_act && r->hf_act_over_lambda) h = h / lam;
+            x *= h;
+        }
+        v[s] = x;
+    }
+    qsort(v, (size_t)S, sizeof(double), orc_cmp_double);
+    double med = (S % 2) ? v[S / 2] : 0.5 * (v[S / 2 - 1] + v[S / 2]);
+    free(v);
+    return (double)(float)med;
+}
+
+int orc_sample(int n_genes, int n_edges, const int32_t* src, const int32_t* dst, const int8_t* sign,
+               const orc_ranges* r, uint64_t seed, int64_t set_begin, int64_t n_sets, int32_t n_ic,
+               float* G, float* k, float* T, float* lam, uint8_t* n, float* ic) {
     if (n_genes < 1 || n_edges < 0 || n_sets < 0 || n_ic < 0) return -1;
-    const double M = orc_gk_median(r);
+    if (r->method != ORC_UNIFORM && r->method != ORC_SOBOL && r->method != ORC_LHS) return -1;
+    if (r->threshold_rule != ORC_T_PRIOR_MEDIAN && r->threshold_rule != ORC_T_HALF_FUNCTIONAL) return -1;
     const int64_t N = n_genes, E = n_edges;
+    if (r->method == ORC_SOBOL && (2 * N + 3 * E > ORC_SOBOL_MAX_DIM || set_begin + n_sets > (1ll << 32)))
+        return -1;
+    const int64_t lhs_n = r->lhs_total > 0 ? r->lhs_total : set_begin + n_sets;
+    if (r->method == ORC_LHS && lhs_n < set_begin + n_sets) return -1;
+    /* Threshold scale per edge: the fixed value, the prior median, or the
+     * half-functional median of the edge's source. */
+    double* scale = (double*)malloc(sizeof(double) * (size_t)(E > 0 ? E : 1));
+    const double M0 = orc_gk_median(r);
+    for (int64_t e = 0; e < E; ++e) {
+        scale[e] = M0;
+        if (r->t_median <= 0 && r->threshold_rule == ORC_T_HALF_FUNCTIONAL) {
+            int32_t na = 0, nh = 0;
+            for (int64_t f = 0; f < E; ++f)
+                if (dst[f] == src[e]) {
+                    if (sign[f] > 0) ++na; else ++nh;
+                }
+            scale[e] = orc_hf_median(r, na, nh);
+        }
+    }
     for (int64_t j = 0; j < n_sets; ++j) {
         const uint64_t p = (uint64_t)(set_begin + j);
         for (int64_t i = 0; i < N; ++i) {
-            double u = orc_uniform(seed, p, (uint64_t)i, 0);
+            double u = orc_unit(r, seed, p, (uint64_t)i, 0, lhs_n);
             G[i * n_sets + j] = (float)(r->g_min + (r->g_max - r->g_min) * u);
-            u = orc_uniform(seed, p, (uint64_t)(N + i), 0);
+            u = orc_unit(r, seed, p, (uint64_t)(N + i), 0, lhs_n);
             k[i * n_sets + j] = (float)(r->k_min + (r->k_max - r->k_min) * u);
         }
         for (int64_t e = 0; e < E; ++e) {
             uint64_t base = (uint64_t)(2 * N + 3 * e);
-            /* Threshold: uniform in [t_lo, t_hi] times the median of G/k. */
-            double u = orc_uniform(seed, p, base, 0);
-            T[e * n_sets + j] = (float)(M * (r->t_lo + (r->t_hi - r->t_lo) * u));
+            /* Threshold: uniform in [t_lo, t_hi] times the source's scale. */
+            double u = orc_unit(r, seed, p, base, 0, lhs_n);
+            T[e * n_sets + j] = (float)(scale[e] * (r->t_lo + (r->t_hi - r->t_lo) * u));
             /* Hill coefficient: integer, uniform over n_min..n_max. */
-            u = orc_uniform(seed, p, base + 1, 0);
+            u = orc_unit(r, seed, p, base + 1, 0, lhs_n);
             int32_t span = r->n_max - r->n_min + 1;
             int32_t off = (int32_t)floor(u * span);
             if (off > span - 1) off = span - 1;
             n[e * n_sets + j] = (uint8_t)(r->n_min + off);
             /* Fold change: activation uniform in its range; inhibition uniform
              * in the inverse range, then inverted. */
-            u = orc_uniform(seed, p, base + 2, 0);
+            u = orc_unit(r, seed, p, base + 2, 0, lhs_n);
             double l;
             if (sign[e] > 0) {
                 l = r->lam_act_min + (r->lam_act_max - r->lam_act_min) * u;
@@ -174,11 +414,13 @@ int orc_sample(int n_genes, int n_edges, const int8_t* sign, const orc_ranges* r
             lam[e * n_sets + j] = (float)l;
         }
     }
+    free(scale);
     if (ic) {
-        /* Initial conditions: fractions of each node's range, shared by all sets. */
+        /* Initial conditions: fractions of each node's range, shared by all
+         * sets; a Latin hypercube over the n_ic conditions. */
         for (int64_t c = 0; c < n_ic; ++c)
             for (int64_t i = 0; i < N; ++i)
-                ic[c * N + i] = (float)orc_uniform(seed, (uint64_t)c, (uint64_t)i, 1);
+                ic[c * N + i] = (float)orc_unit(r, seed, (uint64_t)c, (uint64_t)i, 1, n_ic);
     }
     return 0;
 }

@@ -36,20 +36,46 @@ void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t ou
 int orc_canonicalize(int n_genes, int n_edges, const int32_t* src, const int32_t* dst,
                      const int8_t* sign, int32_t* out_src, int32_t* out_dst, int8_t* out_sign);
 
-/* Sampling ranges; values <= 0 in t_median ask for the prior median of G/k. */
+/* Sampling configuration: Table 1 ranges, the threshold rule and the
+ * generator of the unit-cube points (Sec. 2.1.2).  t_median > 0 fixes the
+ * threshold scale of every edge; otherwise it follows threshold_rule. */
 typedef struct {
     double g_min, g_max, k_min, k_max;
     double lam_act_min, lam_act_max, lam_inh_min, lam_inh_max;
     int32_t n_min, n_max;
     double t_lo, t_hi, t_median;
+    int32_t method;          /* ORC_UNIFORM, ORC_SOBOL or ORC_LHS */
+    int32_t threshold_rule;  /* ORC_T_PRIOR_MEDIAN or ORC_T_HALF_FUNCTIONAL */
+    int32_t hf_samples;      /* Monte Carlo samples per in-degree class (> 0) */
+    int32_t hf_act_over_lambda; /* activating terms over lambda in the estimate */
+    int64_t lhs_total;       /* sets in the Latin hypercube (0: set_begin + n_sets) */
 } orc_ranges;
+
+enum { ORC_UNIFORM = 0, ORC_SOBOL = 1, ORC_LHS = 2 };
+enum { ORC_T_PRIOR_MEDIAN = 0, ORC_T_HALF_FUNCTIONAL = 1 };
+
+/* Threshold scale of edges leaving a gene with n_act activating and n_inh
+ * inhibitory regulators under the half-functional rule (its median level). */
+double orc_hf_median(const orc_ranges* r, int32_t n_act, int32_t n_inh);
+
+/* The q-th coordinate of Sobol' point i before any shift, as a 32-bit
+ * fraction (dimension 0 is van der Corput).  Returns -1 beyond the supported
+ * dimensions. */
+int orc_sobol_u32(int64_t i, int32_t q, uint32_t* out);
+
+/* Number of primitive polynomials of degree s found by the enumeration. */
+int orc_primitive_count(int32_t s);
+
+/* The Latin-hypercube permutation of dimension q over n items. */
+int64_t orc_lhs_perm(uint64_t seed, int32_t domain, int32_t q, int64_t n, int64_t i);
 
 void orc_default_ranges(orc_ranges* r);
 double orc_gk_median(const orc_ranges* r);
 
 /* Sample sets [set_begin, set_begin+n_sets) into arrays of stride n_sets, and
  * n_ic initial-condition fractions ic[c*N + i] (ic may be NULL). */
-int orc_sample(int n_genes, int n_edges, const int8_t* sign_canon, const orc_ranges* r,
+int orc_sample(int n_genes, int n_edges, const int32_t* src_canon, const int32_t* dst_canon,
+               const int8_t* sign_canon, const orc_ranges* r,
                uint64_t seed, int64_t set_begin, int64_t n_sets, int32_t n_ic,
                float* G, float* k, float* T, float* lam, uint8_t* n, float* ic);
 

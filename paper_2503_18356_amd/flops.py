@@ -45,3 +45,21 @@ def algorithmic_bytes(n_genes: int, n_edges: int, n_sets: int, n_ic: int, x_byte
     per_set = (2 * n_genes + 2 * n_edges) * 4 + n_edges
     per_traj = n_genes * x_bytes * (n_t if n_t else 1) + 8 + 1 + 4 + 4
     return float(per_set * n_sets + n_genes * 4 * n_ic + per_traj * n_sets * n_ic)
+
+
+def postproc_bytes(n_genes: int, n_sets: int, n_ic: int, n_bins: int = 64,
+                   capacity: int = 1 << 16) -> int:
+    """Algorithmic HBM bytes of the device post-processing chain on a
+    steady-state result of n_sets * n_ic rows: normalise (read x, G and k per
+    set, write y), histogram (read y and status), levels and codes (read y
+    and status, write one byte per level and eight per code), multistability
+    (read codes, write the per-set state lists and counts), state counts
+    (read codes; write and read the hash table and the sorted output)."""
+    rows = n_sets * n_ic
+    el = rows * n_genes
+    normalise = el * 4 * 2 + n_sets * n_genes * 8
+    hist = el * 4 + rows + n_bins * 8
+    disc = el * 4 + rows + el + rows * 8
+    multi = rows * 8 * 2 + n_sets * 4
+    counts = rows * 8 + capacity * 16 * 3
+    return int(normalise + hist + disc + multi + counts)

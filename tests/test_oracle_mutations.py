@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_pins as pins
+from tests import test_oracle_sampler as sampler
 from tests import test_oracle_tsit5 as tsit5
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle")
@@ -55,6 +56,20 @@ MUTATIONS = [
      [tsit5.test_tableau_order_conditions]),
     ("tsit5 row 7 weight b6", "2.324710524099774},", "2.324701524099774},",
      [tsit5.test_tableau_order_conditions]),
+    ("sobol recurrence drops a term", "uint64_t v = m[k - s] ^ (m[k - s] << s);",
+     "uint64_t v = m[k - s] << s;",
+     [lambda: sampler.test_sobol_each_dimension_is_a_0m1_net(5),
+      lambda: sampler.test_sobol_pairs_meet_the_t_value_bound(3, 7)]),
+    ("primitive test skips a factor", "if (orc_gf2_xpow(order / f, poly, s) == 1) return 0;", "",
+     [lambda: sampler.test_primitive_polynomial_counts(6)]),
+    ("sobol digital shift ignored",
+     "return (double)(v ^ orc_sobol_shift(seed, domain, (int32_t)q)) * 0x1.0p-32;",
+     "return (double)v * 0x1.0p-32;",
+     [sampler.test_sobol_sampler_is_stratified_and_shifted_by_seed]),
+    ("lhs jitter dropped", "return ((double)cell + jitter) / (double)lhs_n;",
+     "return ((double)cell) / (double)lhs_n;", [sampler.test_lhs_sampler_one_point_per_stratum]),
+    ("half-functional activation not over lambda", "if (e < n_act && r->hf_act_over_lambda) h = h / lam;",
+     "", [lambda: sampler.test_half_functional_median_matches_independent_monte_carlo(1, 0)]),
 ]
 
 
