@@ -113,9 +113,55 @@ typedef struct {
                                         [1/max, 1/min] and inverted */
     int32_t n_min, n_max;         /* integer Hill coefficient: [1, 6] */
     double t_lo, t_hi;            /* threshold window: [0.02, 1.98] x median */
-    double t_median;              /* <= 0: the median of G/k implied by the
-                                     G and k ranges (1010/11 for Table 1) */
+    double t_median;              /* > 0: fixed threshold scale of every edge;
+                                     <= 0: follow threshold_rule */
+    int32_t method;               /* unit-cube generator: RAC_SAMPLE_UNIFORM
+                                     (default), RAC_SAMPLE_SOBOL, RAC_SAMPLE_LHS */
+    int32_t threshold_rule;       /* RAC_THRESHOLD_PRIOR_MEDIAN (default) or
+                                     RAC_THRESHOLD_HALF_FUNCTIONAL */
+    int32_t hf_samples;           /* Monte Carlo draws per in-degree class of the
+                                     half-functional rule (default 65536) */
+    int32_t hf_act_over_lambda;   /* 1 (default): activating terms over lambda in
+                                     that estimate, as in Eq. 1 */
+    int64_t lhs_total;            /* sets in the Latin hypercube; 0 = set_begin +
+                                     n_sets (a design over exactly this call) */
 } rac_ranges;
+
+/* Unit-cube generators (Sec. 2.1.2).  Parameter set p is point p of the
+ * generator in 2N + 3E dimensions (slot order: G_i, k_i for i < N, then T_e,
+ * n_e, lambda_e for each canonical edge); initial condition c is point c of a
+ * second design in N dimensions.
+ *  UNIFORM: Philox4x64-10 draws as described at rac_sample_params.
+ *  SOBOL: a Sobol' sequence indexed directly by p (p < 2^32, at most 4096
+ *   dimensions).  Dimension 0 is van der Corput; dimension q >= 1 takes the
+ *   (q-1)-th primitive polynomial over GF(2) in order of degree, then value,
+ *   with initial direction numbers m_k = 2 (w mod 2^(k-1)) + 1, w = word 0 of
+ *   Philox at counter (q, k, 0, 0), key (0x536F626F6C2D6D6B, 0), and Bratley
+ *   and Fox's recurrence after them; 32-bit points XOR a digital shift (the top
+ *   half of word 0 of Philox at counter (q, 0, 2 + domain, 0), key (seed, 0);
+ *   domain 0 parameters, 1 initial conditions), scaled by 2^-32.
+ *  LHS: u = (perm_q(p) + v) / n with v a Philox draw at counter (p, q / 4,
+ *   6 + domain, 0) and perm_q a bijection of [0, n): starting from p, apply
+ *   four rounds of (xor key word r, multiply by 0x9E3779B97F4A7C15, xor with
+ *   itself shifted right by max(1, w / 2)) on w-bit words (2^w >= n, keys = the Philox
+ *   block at counter (q, 0, 4 + domain, 0), key (seed, 0)) until the value
+ *   falls below n.  n = lhs_total for parameters and n_ic for initial
+ *   conditions. */
+typedef enum { RAC_SAMPLE_UNIFORM = 0, RAC_SAMPLE_SOBOL = 1, RAC_SAMPLE_LHS = 2 } rac_sample_method;
+
+/* Threshold rules (Sec. 2.1.2).  PRIOR_MEDIAN: T_e = U[t_lo, t_hi] times the
+ * prior median of G/k.  HALF_FUNCTIONAL: T_e = U[t_lo, t_hi] times the median
+ * level of the edge's source gene given its in-degree (a activating, h
+ * inhibitory regulators): unregulated sources use the prior median of G/k;
+ * otherwise the level is estimated one step deep, x = (G/k) times the
+ * product over its in-edges of H^S(B; T, n, lambda) (over lambda for
+ * activation when hf_act_over_lambda), with B = G'/k' an unregulated level
+ * and T, n, lambda from their priors (T with the prior median), by
+ * hf_samples Monte Carlo draws (Philox counter (a, h, s, d / 4), key
+ * (0x48616C662D66756E, 0), word d % 4, draws in the order G, k, then per
+ * in-edge G', k', T, n, lambda, activating in-edges first); the median of the
+ * draws rounded to FP32. */
+typedef enum { RAC_THRESHOLD_PRIOR_MEDIAN = 0, RAC_THRESHOLD_HALF_FUNCTIONAL = 1 } rac_threshold_rule;
 
 /* Table 1 defaults. */
 void rac_default_ranges(rac_ranges* r);
@@ -145,8 +191,12 @@ typedef struct {
  * of G/k (the half-functional window of Sec. 2.1.2 with the prior median).
  * Initial-condition fractions ic_frac[c * N + i] (host, may be NULL) in
  * [0, 1) use counter (c, i / 4, 1, 0): they are shared by all parameter sets
- * (Sec. 3.1).  out->n_sets must equal n_sets.  ranges NULL = Table 1.
- * EINVAL: NULL arrays, n_sets < 0, n_ic < 0, or inverted/non-positive ranges. */
+ * (Sec. 3.1).  out->n_sets must equal n_sets.  ranges NULL = Table 1 with
+ * uniform draws and the prior-median threshold rule; other generators and the
+ * half-functional rule are chosen in the ranges.
+ * EINVAL: NULL arrays, n_sets < 0, n_ic < 0, inverted/non-positive ranges,
+ * unknown method or rule, hf_samples < 1, lhs_total below set_begin + n_sets.
+ * EUNSUPPORTED: Sobol' beyond 4096 dimensions or 2^32 points. */
 rac_status rac_sample_params(const rac_topology* topo, const rac_ranges* ranges, uint64_t seed,
                              int64_t set_begin, int64_t n_sets, int32_t n_ic,
                              rac_params_view* out, float* ic_frac);

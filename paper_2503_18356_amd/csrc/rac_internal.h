@@ -81,6 +81,20 @@ Shape pick_shape(int epl, int gpl, int precision);
 bool plan_fits(const rac_topology* t, int lpt, int precision);
 int auto_lanes(const rac_topology* t, int precision);
 
+// Per-call tables of the sampler (host and device use the same ones).
+struct SampleTables {
+    int method = RAC_SAMPLE_UNIFORM;
+    std::vector<double> scale;                // per edge: threshold scale
+    const uint32_t* sobol_v = nullptr;        // [kSobolDims][32] direction numbers
+    std::vector<uint32_t> shift0, shift1;     // Sobol' shifts per dimension
+    std::vector<uint64_t> lhs_key0, lhs_key1; // 4 LHS round keys per dimension
+    int64_t lhs_n0 = 0, lhs_n1 = 0;           // Latin hypercube sizes
+    int lhs_w0 = 1, lhs_w1 = 1;               // their word widths
+};
+constexpr int kSobolDims = 4096;
+rac_status make_sample_tables(const rac_topology* t, const rac_ranges& r, uint64_t seed, int64_t set_begin,
+                              int64_t n_sets, int32_t n_ic, SampleTables* out);
+
 // Device copy of a plan on the current device (cached in the handle).
 rac_status get_device_plan(const rac_topology* t, int lpt, const DevicePlan** out);
 void free_device_plans(rac_topology* t);

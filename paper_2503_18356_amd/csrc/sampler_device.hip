@@ -5,9 +5,11 @@
 // rounded IEEE operation (no contraction into fused multiply-adds).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "rac_internal.h"
 
@@ -52,7 +54,50 @@ struct SampleArgs {
     int32_t n_min, n_span;
     float *G, *k, *T, *lam, *ic;
     uint8_t* n;
+    // Generator tables (device; NULL for uniform draws with one threshold scale).
+    int32_t method;
+    const double* scale;      // [E] threshold scale per edge, or NULL: all M
+    const uint32_t* sobol_v;  // [dims][32]
+    const uint32_t* shift0;   // [2N + 3E]
+    const uint32_t* shift1;   // [N]
+    const uint64_t* key0;     // [2N + 3E][4]
+    const uint64_t* key1;     // [N][4]
+    int64_t lhs_n0, lhs_n1;
+    int32_t lhs_w0, lhs_w1;
 };
+
+__device__ uint64_t lhs_cell(uint64_t x, const uint64_t* key, int w, uint64_t n) {
+    const uint64_t mask = w >= 64 ? ~0ull : (1ull << w) - 1;
+    const int sh = w / 2 > 0 ? w / 2 : 1;
+    do {
+        for (int r = 0; r < 4; ++r) {
+            x = (x ^ key[r]) & mask;
+            x = (x * 0x9E3779B97F4A7C15ull) & mask;
+            x ^= x >> sh;
+        }
+    } while (x >= n);
+    return x;
+}
+
+// The unit-cube coordinate of slot q for item a (domain 0 parameter sets,
+// 1 initial conditions), as on the host.
+__device__ double unit(const SampleArgs& a, uint64_t item, uint64_t q, int domain) {
+    if (a.method == RAC_SAMPLE_SOBOL) {
+        uint32_t x = 0;
+        const uint32_t* v = a.sobol_v + q * 32;
+        for (int b = 0; b < 32; ++b)
+            if ((item >> b) & 1) x ^= v[b];
+        x ^= domain ? a.shift1[q] : a.shift0[q];
+        return (double)x * (1.0 / 4294967296.0);
+    }
+    if (a.method == RAC_SAMPLE_LHS) {
+        const uint64_t* key = (domain ? a.key1 : a.key0) + 4 * q;
+        const int64_t n = domain ? a.lhs_n1 : a.lhs_n0;
+        const uint64_t cell = lhs_cell(item, key, domain ? a.lhs_w1 : a.lhs_w0, (uint64_t)n);
+        return __ddiv_rn(__dadd_rn((double)cell, draw(a.seed, item, q, 6 + domain)), (double)n);
+    }
+    return draw(a.seed, item, q, domain);
+}
 
 __global__ __launch_bounds__(256) void sample_kernel(SampleArgs a) {
     const int64_t slots = 2 * (int64_t)a.N + 3 * (int64_t)a.E;
@@ -63,7 +108,7 @@ __global__ __launch_bounds__(256) void sample_kernel(SampleArgs a) {
         const int64_t j = id % a.n_sets;
         const int64_t q = id / a.n_sets;
         const uint64_t p = (uint64_t)(a.set_begin + j);
-        const double u = draw(a.seed, p, (uint64_t)q, 0);
+        const double u = unit(a, p, (uint64_t)q, 0);
         if (q < a.N) {
             a.G[q * a.n_sets + j] = (float)lin(a.g_min, a.g_span, u);
         } else if (q < 2 * a.N) {
@@ -71,7 +116,7 @@ __global__ __launch_bounds__(256) void sample_kernel(SampleArgs a) {
         } else {
             const int64_t r = q - 2 * a.N, e = r / 3, which = r % 3;
             if (which == 0) {
-                a.T[e * a.n_sets + j] = (float)__dmul_rn(a.M, lin(a.t_lo, a.t_span, u));
+                a.T[e * a.n_sets + j] = (float)__dmul_rn(a.scale ? a.scale[e] : a.M, lin(a.t_lo, a.t_span, u));
             } else if (which == 1) {
                 int32_t kk = (int32_t)floor(__dmul_rn(u, (double)a.n_span));
                 if (kk > a.n_span - 1) kk = a.n_span - 1;
@@ -88,7 +133,7 @@ __global__ __launch_bounds__(256) void sample_kernel(SampleArgs a) {
         for (int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; id < nic;
              id += (int64_t)gridDim.x * blockDim.x) {
             const int64_t c = id / a.N, i = id % a.N;
-            a.ic[id] = (float)draw(a.seed, (uint64_t)c, (uint64_t)i, 1);
+            a.ic[id] = (float)unit(a, (uint64_t)c, (uint64_t)i, 1);
         }
     }
 }
@@ -152,10 +197,60 @@ extern "C" rac_status rac_sample_params_device(const rac_topology* topo, const r
     a.lam = dev_out->lam;
     a.n = dev_out->n;
     a.ic = dev_ic_frac;
+    a.method = r.method;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    SampleTables tb;
+    st = make_sample_tables(topo, r, seed, set_begin, n_sets, n_ic, &tb);
+    if (st != RAC_OK) return st;
+    bool one_scale = true;
+    for (double v : tb.scale) one_scale = one_scale && v == a.M;
+    char* dev_block = nullptr;
+    if (r.method != RAC_SAMPLE_UNIFORM || !one_scale) {
+        // One upload of every table the kernel reads; the staging copy is
+        // freed by a host callback once the copy has run.
+        const int64_t D = 2 * N + 3 * E;
+        const int64_t dims = r.method == RAC_SAMPLE_SOBOL ? std::max(D, N) : 0;
+        auto* host = new std::vector<char>();
+        auto put = [&](const void* src, size_t bytes) {
+            const size_t off = (host->size() + 15) / 16 * 16;
+            host->resize(off + bytes);
+            if (bytes) std::memcpy(host->data() + off, src, bytes);
+            return off;
+        };
+        const size_t o_scale = put(tb.scale.data(), tb.scale.size() * sizeof(double));
+        const size_t o_v = put(tb.sobol_v, (size_t)dims * 32 * sizeof(uint32_t));
+        const size_t o_s0 = put(tb.shift0.data(), tb.shift0.size() * sizeof(uint32_t));
+        const size_t o_s1 = put(tb.shift1.data(), tb.shift1.size() * sizeof(uint32_t));
+        const size_t o_k0 = put(tb.lhs_key0.data(), tb.lhs_key0.size() * sizeof(uint64_t));
+        const size_t o_k1 = put(tb.lhs_key1.data(), tb.lhs_key1.size() * sizeof(uint64_t));
+        hipError_t he = hipMallocAsync((void**)&dev_block, std::max<size_t>(host->size(), 16), stream);
+        if (he == hipSuccess)
+            he = hipMemcpyAsync(dev_block, host->data(), host->size(), hipMemcpyHostToDevice, stream);
+        if (he == hipSuccess)
+            he = hipLaunchHostFunc(stream, [](void* p) { delete static_cast<std::vector<char>*>(p); }, host);
+        else
+            delete host;
+        if (he != hipSuccess)
+            return fail(RAC_EDEVICE, std::string("sampler table upload: ") + hipGetErrorString(he));
+        a.scale = (const double*)(dev_block + o_scale);
+        a.sobol_v = (const uint32_t*)(dev_block + o_v);
+        a.shift0 = (const uint32_t*)(dev_block + o_s0);
+        a.shift1 = (const uint32_t*)(dev_block + o_s1);
+        a.key0 = (const uint64_t*)(dev_block + o_k0);
+        a.key1 = (const uint64_t*)(dev_block + o_k1);
+        a.lhs_n0 = tb.lhs_n0;
+        a.lhs_n1 = tb.lhs_n1;
+        a.lhs_w0 = tb.lhs_w0;
+        a.lhs_w1 = tb.lhs_w1;
+    }
     const int64_t work = std::max<int64_t>((2 * N + 3 * E) * n_sets, (int64_t)n_ic * N);
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((work + 255) / 256, 65536));
-    hipLaunchKernelGGL(sample_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)hip_stream, a);
+    hipLaunchKernelGGL(sample_kernel, dim3(blocks), dim3(256), 0, stream, a);
     hipError_t e = hipGetLastError();
+    if (dev_block) {
+        hipError_t fe = hipFreeAsync(dev_block, stream);
+        if (e == hipSuccess) e = fe;
+    }
     if (e != hipSuccess) return fail(RAC_EDEVICE, std::string("sample kernel launch: ") + hipGetErrorString(e));
     return RAC_OK;
 }

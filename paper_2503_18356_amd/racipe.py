@@ -23,6 +23,8 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4
 CONVERGED, T_END, MAX_STEPS, STEP_UNDERFLOW, NONFINITE = range(5)
 FP32, FP64 = 0, 1
 DP5, TSIT5 = 0, 1  # rac_method
+SAMPLE_UNIFORM, SAMPLE_SOBOL, SAMPLE_LHS = 0, 1, 2  # rac_sample_method
+PRIOR_MEDIAN, HALF_FUNCTIONAL = 0, 1  # rac_threshold_rule
 STATUS_NAMES = ["CONVERGED", "T_END", "MAX_STEPS", "STEP_UNDERFLOW", "NONFINITE"]
 
 
@@ -37,7 +39,9 @@ class _Ranges(C.Structure):
                 ("k_max", C.c_double), ("lam_act_min", C.c_double), ("lam_act_max", C.c_double),
                 ("lam_inh_min", C.c_double), ("lam_inh_max", C.c_double), ("n_min", C.c_int32),
                 ("n_max", C.c_int32), ("t_lo", C.c_double), ("t_hi", C.c_double),
-                ("t_median", C.c_double)]
+                ("t_median", C.c_double), ("method", C.c_int32), ("threshold_rule", C.c_int32),
+                ("hf_samples", C.c_int32), ("hf_act_over_lambda", C.c_int32),
+                ("lhs_total", C.c_int64)]
 
 
 class _ParamsView(C.Structure):
@@ -206,6 +210,11 @@ class Ranges:
     t_lo: float = 0.02
     t_hi: float = 1.98
     t_median: float = 0.0
+    method: int = 0             # SAMPLE_UNIFORM, SAMPLE_SOBOL, SAMPLE_LHS
+    threshold_rule: int = 0     # PRIOR_MEDIAN, HALF_FUNCTIONAL
+    hf_samples: int = 65536
+    hf_act_over_lambda: int = 1
+    lhs_total: int = 0
 
     def c(self) -> _Ranges:
         return _Ranges(*[getattr(self, f[0]) for f in _Ranges._fields_])

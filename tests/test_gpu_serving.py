@@ -47,6 +47,19 @@ def test_device_sampler_custom_ranges():
         assert np.array_equal(getattr(h, f), getattr(d, f).cpu().numpy()), f
 
 
+@pytest.mark.parametrize("rule", [rp.PRIOR_MEDIAN, rp.HALF_FUNCTIONAL])
+@pytest.mark.parametrize("method", [rp.SAMPLE_UNIFORM, rp.SAMPLE_SOBOL, rp.SAMPLE_LHS])
+def test_device_sampler_all_generators(method, rule):
+    T = rp.Topology.from_inputs(inputs.dense_core(1004))
+    r = rp.Ranges(method=method, threshold_rule=rule, hf_samples=4096, lhs_total=5000)
+    for begin, P, n_ic in [(0, 3000, 9), (4000, 1000, 2)]:
+        h = rp.sample_params(T, 77, P, n_ic, set_begin=begin, ranges=r)
+        d = rp.sample_params_device(T, 77, P, n_ic, set_begin=begin, ranges=r)
+        torch.cuda.synchronize()
+        for f in ("G", "k", "T", "lam", "n", "ic"):
+            assert np.array_equal(getattr(h, f), getattr(d, f).cpu().numpy()), (f, method, rule)
+
+
 def _direct(T, params, lanes):
     out = rp.steady_states(T, params, rp.Opts(precision=rp.FP32, lanes_per_traj=lanes))
     torch.cuda.synchronize()

@@ -1,0 +1,40 @@
+"""The library's host sampler against the oracle's, bit for bit, for every
+unit-cube generator and threshold rule (CPU).  The two share no code: each
+implements the Sobol' construction, the Latin-hypercube permutations and the
+half-functional Monte Carlo from the definitions in include/rac.h."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_18356_amd import inputs
+from paper_2503_18356_amd import racipe as rp
+
+TOPOS = [inputs.toggle_switch(), inputs.toggle_switch_self_activation(),
+         inputs.erdos_renyi(10, 25, 1002), inputs.dense_core(1004)]
+
+
+@pytest.mark.parametrize("rule", [rp.PRIOR_MEDIAN, rp.HALF_FUNCTIONAL])
+@pytest.mark.parametrize("method", [rp.SAMPLE_UNIFORM, rp.SAMPLE_SOBOL, rp.SAMPLE_LHS])
+@pytest.mark.parametrize("topo", TOPOS, ids=[t.name for t in TOPOS])
+def test_host_sampler_bit_exact_with_oracle(topo, method, rule):
+    T = rp.Topology.from_inputs(topo)
+    net = oracle.canonicalize(topo.n_genes, topo.src, topo.dst, topo.sign)
+    kw = dict(method=method, threshold_rule=rule, hf_samples=4096, lhs_total=500)
+    for begin, P, n_ic in [(0, 200, 7), (300, 200, 3)]:
+        h = rp.sample_params(T, 1234, P, n_ic, set_begin=begin, ranges=rp.Ranges(**kw))
+        o = oracle.sample(net, 1234, P, n_ic, set_begin=begin, ranges=oracle.Ranges(**kw))
+        for f in ("G", "k", "T", "lam", "n", "ic"):
+            assert np.array_equal(getattr(h, f), getattr(o, f)), f
+
+
+def test_bad_sampler_choices_are_rejected():
+    T = rp.Topology.from_inputs(inputs.toggle_switch())
+    for kw in (dict(method=3), dict(threshold_rule=2), dict(hf_samples=0),
+               dict(method=rp.SAMPLE_LHS, lhs_total=10)):
+        with pytest.raises(rp.RacError) as e:
+            rp.sample_params(T, 1, 20, 1, ranges=rp.Ranges(**kw))
+        assert e.value.code == rp.EINVAL
+    big = rp.Topology.from_inputs(inputs.erdos_renyi(100, 1500, 3))   # 3200 + 4500 dims
+    with pytest.raises(rp.RacError) as e:
+        rp.sample_params(big, 1, 2, 1, ranges=rp.Ranges(method=rp.SAMPLE_SOBOL))
+    assert e.value.code == rp.EUNSUPPORTED
