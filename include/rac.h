@@ -406,6 +406,46 @@ rac_status rac_state_counts(const uint64_t* dev_codes, int64_t n_rows, int64_t c
                             uint64_t* dev_keys, int64_t* dev_counts, int64_t* dev_n_unique,
                             void* hip_stream);
 
+/* ------------------------------------------------------------------------ */
+/* Boolean Ising formalism (Eq. 3).                                           */
+/* ------------------------------------------------------------------------ */
+/* Gene i's next state is on when sum_j J_ij s_j > 0, off when < 0 and
+ * unchanged when 0, with J_ij = +1 for an activating edge j -> i, -1 for an
+ * inhibiting one; an off gene counts as `low` (0 or -1) in the sums.
+ * States are bit-packed, [n_traj][W] u64 with W = ceil(N / 64) and gene i in
+ * bit i % 64 of word i / 64 (N <= 256).
+ *  SYNC: every gene updates at once; a trajectory stops at the first state
+ *   that maps to itself (steps = updates done) or after max_steps updates.
+ *  ASYNC: one gene per update, cycled from `order` (host array of order_len
+ *   gene indices) or chosen at random: update u of trajectory t takes the
+ *   low (u even) or high (u odd) 32-bit half h of word (u % 8) / 2 of Philox
+ *   at counter (t, u / 8, 8, 0), key (seed, 0), and picks gene (h N) >> 32.
+ *   The state is tested for being a fixed point of the synchronous map at
+ *   the start and every check_every updates (0: N); the first pass stops it.
+ * Without dev_init, gene i of trajectory t starts on when the top bit of word
+ * i % 4 of Philox at counter (t, i / 4, 9, 0), key (seed, 0) is set.
+ * Outputs: dev_final[n_traj][W]; dev_steps[n_traj] (i32) and dev_status
+ * [n_traj] (i8: 0 fixed point reached, 1 max_steps) may be NULL.
+ * EINVAL: bad mode or low, negative counts, order entries outside [0, N),
+ * NULL outputs.  EUNSUPPORTED: N > 256. */
+typedef enum { RAC_ISING_SYNC = 0, RAC_ISING_ASYNC = 1 } rac_ising_mode;
+
+typedef struct {
+    int32_t mode;           /* RAC_ISING_SYNC (default) or RAC_ISING_ASYNC */
+    int32_t low;            /* value of an off gene in the sums: 0 (default) or -1 */
+    int32_t max_steps;      /* updates per trajectory (default 1000) */
+    int32_t check_every;    /* asynchronous fixed-point test interval; 0 = N */
+    uint64_t seed;          /* random gene choices and random initial states */
+    const int32_t* order;   /* asynchronous update order (host), or NULL */
+    int32_t order_len;
+} rac_ising_opts;
+
+void rac_default_ising_opts(rac_ising_opts* o);
+
+rac_status rac_ising(const rac_topology* topo, const rac_ising_opts* opts, int64_t n_traj,
+                     const uint64_t* dev_init, uint64_t* dev_final, int32_t* dev_steps,
+                     int8_t* dev_status, void* hip_stream);
+
 /* The lanes-per-trajectory choice the library would make for a network
  * (0 if none fits), and whether a given choice fits the compiled kernels. */
 int32_t rac_auto_lanes(const rac_topology* topo, int32_t precision);

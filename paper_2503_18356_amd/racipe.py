@@ -58,6 +58,12 @@ class _Opts(C.Structure):
                 ("refill_min", C.c_int32), ("method", C.c_int32)]
 
 
+class _IsingOpts(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("low", C.c_int32), ("max_steps", C.c_int32),
+                ("check_every", C.c_int32), ("seed", C.c_uint64), ("order", C.c_void_p),
+                ("order_len", C.c_int32)]
+
+
 class _Info(C.Structure):
     _fields_ = [("t_final", C.c_void_p), ("status", C.c_void_p), ("n_accepted", C.c_void_p),
                 ("n_rejected", C.c_void_p)]
@@ -132,6 +138,9 @@ def lib():
         L.rac_multistability.restype = C.c_int
         L.rac_state_counts.argtypes = [vp, i64, i64, vp, vp, vp, vp]
         L.rac_state_counts.restype = C.c_int
+        L.rac_default_ising_opts.argtypes = [C.POINTER(_IsingOpts)]
+        L.rac_ising.argtypes = [vp, C.POINTER(_IsingOpts), i64, vp, vp, vp, vp, vp]
+        L.rac_ising.restype = C.c_int
         _lib = L
     return _lib
 
@@ -534,3 +543,33 @@ def analyse_steady_states(topo: Topology, params: DeviceParams, result: Result, 
     keys, counts, nu = state_counts(cd, capacity, stream=stream)
     return dict(y=y, hist=hist, thresholds=thr, levels=lv, codes=cd, n_states=n_states,
                 states=states, keys=keys, counts=counts, n_unique=nu)
+
+
+# --------------------------------------------------------------------------
+# Boolean Ising formalism (rac_ising).  States travel as int64 tensors of
+# shape [n_traj][W] holding the bit-packed u64 words (gene i: bit i % 64 of
+# word i // 64).
+# --------------------------------------------------------------------------
+ISING_SYNC, ISING_ASYNC = 0, 1
+
+
+def ising(topo: Topology, n_traj: int, mode: int = ISING_SYNC, low: int = 0, max_steps: int = 1000,
+          seed: int = 0, init=None, order=None, check_every: int = 0, device="cuda", stream=None):
+    """(final int64[n_traj][W], steps int32[n_traj], status int8[n_traj]);
+    init: int64[n_traj][W] device tensor or None for seeded random states."""
+    import torch
+    W = (topo.n_genes + 63) // 64
+    fin = torch.empty((n_traj, W), dtype=torch.int64, device=device)
+    steps = torch.empty(n_traj, dtype=torch.int32, device=device)
+    status = torch.empty(n_traj, dtype=torch.int8, device=device)
+    o = _IsingOpts()
+    lib().rac_default_ising_opts(C.byref(o))
+    o.mode, o.low, o.max_steps, o.check_every = mode, low, max_steps, check_every
+    o.seed = seed & (2**64 - 1)
+    ordr = None
+    if order is not None:
+        ordr = np.ascontiguousarray(order, np.int32)
+        o.order, o.order_len = ordr.ctypes.data, ordr.size
+    _check(lib().rac_ising(topo.handle, C.byref(o), n_traj, _ptr(init), fin.data_ptr(), steps.data_ptr(),
+                           status.data_ptr(), _stream_ptr(stream)))
+    return fin, steps, status
