@@ -392,6 +392,51 @@ def bench_core22ts(args, torch, rp, flops, inputs):
     return rec
 
 
+PEAK_INT32 = 256 * 4 * 16 * 2.4e9   # 32-bit VALU lane-ops/s (unpacked)
+
+
+def bench_ising(args, torch, rp, flops, inputs):
+    """Boolean Ising (Eq. 3) on the 22-gene network: 10^6 random initial
+    states, synchronous and asynchronous updates with +-1 states."""
+    topo = inputs.dense_core(1004)
+    T = rp.Topology.from_inputs(topo)
+    n_traj, W = 1_000_000, 1
+    rec = base_record(args)
+    forms = {}
+    stream = torch.cuda.current_stream()
+    for mode, name, max_steps in ((rp.ISING_SYNC, "sync", 1000), (rp.ISING_ASYNC, "async", 20000)):
+        out = {}
+        fn = lambda: out.update(r=rp.ising(T, n_traj, mode, -1, max_steps, seed=7, stream=stream))
+        fn()
+        wall, lat = timed(fn, max(1, args.steps), stream, torch)
+        fin, steps, status = out["r"]
+        sp = steps.cpu().numpy().astype(np.int64)
+        st = status.cpu().numpy()
+        # Gene evaluations: sync N per update plus the final check; async one
+        # per update plus N per fixed-point test (every N updates).
+        N = T.n_genes
+        if mode == rp.ISING_SYNC:
+            evals = int(((sp + 1) * N).sum())
+        else:
+            evals = int((sp + (sp // N + 1) * N).sum())
+        ops = evals * (8 * W + 6)
+        forms[name] = {"trajectories_per_s": n_traj / (lat.mean() * 1e-3), "kernel_ms": float(lat.mean()),
+                       "fixed_point_fraction": float(np.mean(st == 0)),
+                       "mean_updates": float(sp.mean()), "gene_evaluations_per_s": evals / (lat.mean() * 1e-3),
+                       "int_ops_per_s": ops / (lat.mean() * 1e-3), "int_frac": ops / (lat.mean() * 1e-3) / PEAK_INT32}
+    rec.update({"value": forms["sync"]["trajectories_per_s"], "unit": "trajectories/s",
+                "metric": "Boolean Ising trajectories to a fixed point per second",
+                "ms_per_step": forms["sync"]["kernel_ms"],
+                "config": {"workload": "Boolean Ising, 22-gene / 82-edge dense-core network, 1e6 random "
+                                       "initial states, +-1 states, sync (<= 1000 updates) and async "
+                                       "(<= 20000 single-gene updates)"},
+                "forms": forms,
+                "roofline": {"bound": "alu", "achieved": forms["sync"]["int_ops_per_s"] / 1e12,
+                             "peak": PEAK_INT32 / 1e12, "unit": "Tops/s (int32 VALU)",
+                             "frac": forms["sync"]["int_frac"], "traffic": None}})
+    return rec
+
+
 def bench_serve(args, torch, rp, flops, inputs):
     st = serving_run(args.serve_requests, args.serve_warmup, args.serve_rate)
     rec = base_record(args)
@@ -412,7 +457,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="er10", choices=["er10", "ts", "uneven64", "core22ts", "serve"])
+    ap.add_argument("--workload", default="er10", choices=["er10", "ts", "uneven64", "core22ts", "serve", "ising"])
     ap.add_argument("--n-sets", type=int, default=10000)
     ap.add_argument("--n-ic", type=int, default=100)
     ap.add_argument("--lanes", type=int, default=0)
@@ -443,7 +488,7 @@ def main():
     from paper_2503_18356_amd import racipe as rp
 
     fn = {"er10": bench_er10, "ts": bench_ts, "uneven64": bench_uneven64,
-          "core22ts": bench_core22ts, "serve": bench_serve}[args.workload]
+          "core22ts": bench_core22ts, "serve": bench_serve, "ising": bench_ising}[args.workload]
     rec = fn(args, torch, rp, flops, inputs)
     print(json.dumps(rec), flush=True)
 

@@ -9,6 +9,7 @@
 // use fixed IEEE operations (no contraction) so that they are reproducible.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 
@@ -233,27 +234,59 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     return z ^ (z >> 31);
 }
 
-// Open addressing with linear probing; a full table raises the overflow flag.
-__global__ void insert_kernel(const uint64_t* __restrict__ codes, int64_t n, unsigned long long* keys,
+// Add `add` to key c in the global table (open addressing, linear probing);
+// a full table raises the overflow flag.
+__device__ void global_insert(uint64_t c, unsigned long long add, unsigned long long* keys,
                               unsigned long long* counts, uint64_t mask, int* overflow) {
+    uint64_t h = mix64(c) & mask;
+    for (uint64_t probe = 0; probe <= mask; ++probe) {
+        const unsigned long long prev = atomicCAS(&keys[h], (unsigned long long)kNoState, (unsigned long long)c);
+        if (prev == kNoState || prev == c) {
+            atomicAdd(&counts[h], add);
+            return;
+        }
+        h = (h + 1) & mask;
+    }
+    atomicExch(overflow, 1);
+}
+
+// Counts are first gathered in a per-workgroup LDS table, so that only the
+// distinct states of each workgroup reach the global atomics (a few hot
+// states otherwise serialise them); keys that find no LDS slot within a few
+// probes go to the global table directly.
+constexpr int kLocalSlots = 1024;
+constexpr int kLocalProbes = 16;
+
+__global__ __launch_bounds__(kThreads) void insert_kernel(const uint64_t* __restrict__ codes, int64_t n,
+                                                          unsigned long long* keys, unsigned long long* counts,
+                                                          uint64_t mask, int* overflow) {
+    __shared__ unsigned long long lk[kLocalSlots];
+    __shared__ unsigned int lc[kLocalSlots];
+    for (int i = threadIdx.x; i < kLocalSlots; i += blockDim.x) {
+        lk[i] = kNoState;
+        lc[i] = 0;
+    }
+    __syncthreads();
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
          r += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t c = codes[r];
         if (c == kNoState) continue;
-        uint64_t h = mix64(c) & mask;
-        bool done = false;
-        for (uint64_t probe = 0; probe <= mask; ++probe) {
-            const unsigned long long prev = atomicCAS(&keys[h], (unsigned long long)kNoState,
-                                                      (unsigned long long)c);
+        int h = (int)(mix64(c) & (kLocalSlots - 1));
+        bool placed = false;
+        for (int probe = 0; probe < kLocalProbes; ++probe) {
+            const unsigned long long prev = atomicCAS(&lk[h], (unsigned long long)kNoState, (unsigned long long)c);
             if (prev == kNoState || prev == c) {
-                atomicAdd(&counts[h], 1ull);
-                done = true;
+                atomicAdd(&lc[h], 1u);
+                placed = true;
                 break;
             }
-            h = (h + 1) & mask;
+            h = (h + 1) & (kLocalSlots - 1);
         }
-        if (!done) atomicExch(overflow, 1);
+        if (!placed) global_insert(c, 1ull, keys, counts, mask, overflow);
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kLocalSlots; i += blockDim.x)
+        if (lk[i] != kNoState) global_insert(lk[i], lc[i], keys, counts, mask, overflow);
 }
 
 __global__ void compact_kernel(const unsigned long long* keys, const unsigned long long* counts, int64_t cap,
@@ -267,8 +300,47 @@ __global__ void compact_kernel(const unsigned long long* keys, const unsigned lo
     }
 }
 
-// One pass of a bitonic sorting network over n (a power of two) (key, count)
-// pairs in global memory, ascending by key.
+// Bitonic sorting network over n (a power of two) (key, count) pairs,
+// ascending by key.  Passes with stride < kTile run inside one LDS tile of
+// kTile pairs (bitonic_tile: every size up to kTile in the first call, then
+// the short strides of each larger size); longer strides are global passes.
+constexpr int kTile = 2048;
+
+__global__ __launch_bounds__(kThreads) void bitonic_tile(uint64_t* keys, int64_t* vals, int64_t n,
+                                                         int64_t size_lo, int64_t size_hi) {
+    __shared__ uint64_t k[kTile];
+    __shared__ int64_t v[kTile];
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    for (int i = threadIdx.x; i < kTile; i += blockDim.x) {
+        k[i] = keys[base + i];
+        v[i] = vals[base + i];
+    }
+    __syncthreads();
+    for (int64_t size = size_lo; size <= size_hi; size <<= 1) {
+        for (int64_t stride = (size < kTile ? size : kTile) >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < kTile; i += blockDim.x) {
+                const int j = i ^ (int)stride;
+                if (j > i) {
+                    const bool up = ((base + i) & size) == 0;
+                    const uint64_t a = k[i], b = k[j];
+                    if ((a > b) == up) {
+                        k[i] = b;
+                        k[j] = a;
+                        const int64_t t = v[i];
+                        v[i] = v[j];
+                        v[j] = t;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < kTile; i += blockDim.x) {
+        keys[base + i] = k[i];
+        vals[base + i] = v[i];
+    }
+}
+
 __global__ void bitonic_pass(uint64_t* keys, int64_t* vals, int64_t n, int64_t size, int64_t stride) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -409,13 +481,26 @@ rac_status rac_state_counts(const uint64_t* dev_codes, int64_t n_rows, int64_t c
     hipLaunchKernelGGL(fill_kernel<uint64_t>, dim3(g), dim3(kThreads), 0, s, dev_keys, capacity, kNoState);
     hipLaunchKernelGGL(fill_kernel<int64_t>, dim3(g), dim3(kThreads), 0, s, dev_counts, capacity, (int64_t)0);
     if (n_rows > 0)
-        hipLaunchKernelGGL(insert_kernel, dim3(grid_for(n_rows)), dim3(kThreads), 0, s, dev_codes, n_rows, tk, tc,
-                           (uint64_t)(capacity - 1), ovf);
+        hipLaunchKernelGGL(insert_kernel, dim3(std::min(grid_for(n_rows), 1024)), dim3(kThreads), 0, s, dev_codes,
+                           n_rows, tk, tc, (uint64_t)(capacity - 1), ovf);
     hipLaunchKernelGGL(compact_kernel, dim3(g), dim3(kThreads), 0, s, tk, tc, capacity, dev_keys, dev_counts, nu);
-    for (int64_t size = 2; size <= capacity; size <<= 1)
-        for (int64_t stride = size >> 1; stride > 0; stride >>= 1)
-            hipLaunchKernelGGL(bitonic_pass, dim3(g), dim3(kThreads), 0, s, dev_keys, dev_counts, capacity, size,
-                               stride);
+    if (capacity <= kTile) {
+        for (int64_t size = 2; size <= capacity; size <<= 1)
+            for (int64_t stride = size >> 1; stride > 0; stride >>= 1)
+                hipLaunchKernelGGL(bitonic_pass, dim3(g), dim3(kThreads), 0, s, dev_keys, dev_counts, capacity,
+                                   size, stride);
+    } else {
+        const int tiles = (int)(capacity / kTile);
+        hipLaunchKernelGGL(bitonic_tile, dim3(tiles), dim3(kThreads), 0, s, dev_keys, dev_counts, capacity,
+                           (int64_t)2, (int64_t)kTile);
+        for (int64_t size = 2 * kTile; size <= capacity; size <<= 1) {
+            for (int64_t stride = size >> 1; stride >= kTile; stride >>= 1)
+                hipLaunchKernelGGL(bitonic_pass, dim3(g), dim3(kThreads), 0, s, dev_keys, dev_counts, capacity,
+                                   size, stride);
+            hipLaunchKernelGGL(bitonic_tile, dim3(tiles), dim3(kThreads), 0, s, dev_keys, dev_counts, capacity,
+                               size, size);
+        }
+    }
     hipLaunchKernelGGL(finish_counts_kernel, dim3(1), dim3(64), 0, s, nu, ovf, dev_n_unique);
     hipError_t le = hipGetLastError();
     hipError_t fe = hipFreeAsync(ws, s);
