@@ -41,6 +41,23 @@ const KernelEntry* find_kernel(int precision, bool ts, int epl, int gpl, bool bo
     return nullptr;
 }
 
+// Side streams per device (default priority) on which run_jobs overlaps the
+// launches of one call; created on first use and kept for the process.
+static const std::vector<hipStream_t>& side_streams(int dev) {
+    static std::mutex m;
+    static std::map<int, std::vector<hipStream_t>> all;
+    std::lock_guard<std::mutex> lk(m);
+    auto it = all.find(dev);
+    if (it != all.end()) return it->second;
+    std::vector<hipStream_t> v;
+    for (int i = 0; i < 3; ++i) {
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) break;
+        v.push_back(s);
+    }
+    return all[dev] = v;
+}
+
 // A library-owned non-blocking stream per device for small uploads, so that
 // building a plan never waits for (or serialises with) work on user streams.
 static hipStream_t lib_stream(int dev) {
@@ -313,12 +330,50 @@ rac_status run_jobs(std::vector<Job>& jobs, const rac_solver_opts* o, bool ts,
         const Shape s = pick_shape(std::max(lp->epl, 1), lp->gpl, o->precision);
         groups[std::make_tuple(lpt, s.epl, s.gpl)].push_back(j);
     }
-    for (auto& kv : groups) {
-        rac_status st = launch_group(kv.second, std::get<0>(kv.first), o, ts, host_t_out, n_t,
-                                     (hipStream_t)stream);
-        if (st != RAC_OK) return st;
+    hipStream_t main = (hipStream_t)stream;
+    if (groups.size() <= 1) {
+        for (auto& kv : groups) {
+            rac_status st = launch_group(kv.second, std::get<0>(kv.first), o, ts, host_t_out, n_t, main);
+            if (st != RAC_OK) return st;
+        }
+        return RAC_OK;
     }
-    return RAC_OK;
+    // Several launches: largest first, spread over the caller's stream and the
+    // library's side streams (forked from and joined back into the caller's
+    // stream), so that the tail of one persistent launch, when few of its
+    // trajectories remain, is filled by the waves of another.
+    std::vector<std::pair<double, const std::tuple<int, int, int>*>> order;
+    for (auto& kv : groups) {
+        double work = 0;
+        for (const Job& j : kv.second)
+            work += (double)j.params.n_sets * j.n_ic * (j.topo->n_edges + j.topo->n_genes + 1);
+        order.push_back({work, &kv.first});
+    }
+    std::sort(order.begin(), order.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+    int dev = 0;
+    RAC_HIP(hipGetDevice(&dev), "hipGetDevice");
+    const std::vector<hipStream_t>& side = side_streams(dev);
+    if (side.empty()) return fail(RAC_EDEVICE, "side stream creation failed");
+    hipEvent_t fork = nullptr;
+    RAC_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "hipEventCreate");
+    RAC_HIP(hipEventRecord(fork, main), "hipEventRecord");
+    for (hipStream_t sd : side) RAC_HIP(hipStreamWaitEvent(sd, fork, 0), "hipStreamWaitEvent");
+    rac_status st = RAC_OK;
+    for (size_t k = 0; k < order.size() && st == RAC_OK; ++k) {
+        const auto& key = *order[k].second;
+        hipStream_t sk = k % (side.size() + 1) == 0 ? main : side[k % (side.size() + 1) - 1];
+        st = launch_group(groups[key], std::get<0>(key), o, ts, host_t_out, n_t, sk);
+    }
+    // Join: the caller's stream waits for everything enqueued on the side streams.
+    for (hipStream_t sd : side) {
+        hipEvent_t done = nullptr;
+        if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(done, sd) != hipSuccess || hipStreamWaitEvent(main, done, 0) != hipSuccess)
+            st = fail(RAC_EDEVICE, "joining side streams failed");
+        if (done) (void)hipEventDestroy(done);
+    }
+    (void)hipEventDestroy(fork);
+    return st;
 }
 
 }  // namespace
