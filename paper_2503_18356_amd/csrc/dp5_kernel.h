@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
     using O = Ops<R>;
     using NT = typename O::NType;
     using Lay = LdsLayout<R, EPL, GPL>;
-    static_assert(EPL % 4 == 0, "edge slots come in chunks of four");
+    static_assert(EPL >= 1, "at least one edge slot");
     __shared__ R lds[(kBlock / 64) * Lay::kWaveElems];
     char* const lb = reinterpret_cast<char*>(lds);
     auto ld = [&](uint32_t addr) -> R { return *reinterpret_cast<const R*>(lb + addr); };
@@ -247,16 +247,20 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
         for (int q = 0; q < GPL; ++q) st(g_wa[q], O::publish(yv[q]));
         wave_sync();
         R run = 1;
+        // Chunks of up to four independent factors, then their running products.
 #pragma unroll
         for (int c0 = 0; c0 < EPL; c0 += 4) {
             R hv[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                hv[j] = O::hill(ld(e_xa[c0 + j]), e_invT[c0 + j], e_n[c0 + j], e_b[c0 + j], e_d[c0 + j]);
+                if (c0 + j < EPL)
+                    hv[j] = O::hill(ld(e_xa[c0 + j]), e_invT[c0 + j], e_n[c0 + j], e_b[c0 + j], e_d[c0 + j]);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                run *= hv[j];
-                st(pre_base + (uint32_t)(c0 + j + 1) * 64 * SZ, run);
+                if (c0 + j < EPL) {
+                    run *= hv[j];
+                    st(pre_base + (uint32_t)(c0 + j + 1) * 64 * SZ, run);
+                }
             }
         }
         wave_sync();

@@ -12,7 +12,7 @@ namespace rac {
 static const KernelEntry kTable[] = {
     RAC_K(4, 1), RAC_K(4, 2), RAC_K(4, 3), RAC_K(4, 4), RAC_K(4, 6), RAC_K(8, 1), RAC_K(8, 2),
     RAC_K(8, 3), RAC_K(8, 4), RAC_K(12, 1), RAC_K(12, 2), RAC_K(12, 3), RAC_K(16, 1),
-    RAC_K(16, 2),
+    RAC_K(16, 2), RAC_K(7, 3),
 };
 
 int kernels_f64_ss_tsit5(const KernelEntry** out) {
