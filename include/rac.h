@@ -456,6 +456,15 @@ int32_t rac_lanes_supported(const rac_topology* topo, int32_t precision, int32_t
 rac_status rac_plan_shape(const rac_topology* topo, int32_t precision, int32_t lanes, int32_t* epl,
                           int32_t* gpl);
 
+/* Which algebraic form of the Hill factor (Eq. 2) kernels of a precision and
+ * edge-slot count use: 1 for 1 + D / (1 + 2^z) with D >= 0 and the constant
+ * lam (inhibition) or 1/lam (activation over lambda) folded into the
+ * production rate, 0 for sqrt(lam) + (1/sqrt(lam) - sqrt(lam)) / (1 + r).
+ * Both are Eq. 2 rearranged; kernels of the same form and lane count give
+ * bit-identical results whatever their slot counts, kernels of different
+ * forms agree to rounding.  -1 for a bad precision or epl < 1. */
+int32_t rac_factor_form(int32_t precision, int32_t epl);
+
 #ifdef __cplusplus
 }
 #endif

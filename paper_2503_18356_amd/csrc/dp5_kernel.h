@@ -5,6 +5,8 @@
 // units that instantiate it.
 #pragma once
 
+#include <type_traits>
+
 #include "kernel_common.h"
 
 namespace rac {
@@ -168,8 +170,11 @@ enum : int { kRunning = -1 };
 
 // LDS use per wave, in elements of R:
 //   [0, 64*GPL)                 source levels, index gene * n_groups + group
+//                               (gene slot q of lane r holds gene r + q * lpt, so
+//                               its level sits 64 elements after slot q - 1's;
+//                               padding gene slots write levels nobody reads)
 //   [64*GPL, 64*(GPL+EPL+1))    running products, index slot * 64 + lane
-//   [64*(GPL+EPL+1), +64)       one write-only sink per lane (padding slots)
+//   [64*(GPL+EPL+1), +64)       one sink per lane, read by padding edge slots
 // Every address a lane uses is precomputed as an absolute LDS byte offset.
 template <typename R, int EPL, int GPL>
 struct LdsLayout {
@@ -202,6 +207,8 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
     const int r = lane & (lpt - 1);   // lane within the group
     const int gshift = g * lpt;
     const uint64_t glow = lpt == 64 ? ~0ull : ((1ull << lpt) - 1);
+    // Level of gene slot q: pub_base + q * 64 elements.
+    const uint32_t pub_base = (wave_elem + (uint32_t)(r * n_groups + g)) * SZ;
     const Controls& c = a.c;
 
     st(pre_base, (R)1);  // prefix[0] = 1, never overwritten
@@ -211,21 +218,31 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
 
     // Edge slots: source address, threshold term (O::edge_t), n, sqrt(lam),
     // 1/sqrt(lam) - sqrt(lam).
+    // FP32 shapes of up to 16 edge slots use factors 1 + D / (1 + 2^z) with
+    // D >= 0 (no base term; every factor lies in [1, 1 + D], so a lane's
+    // running product stays below 100^16 for Table 1's lambdas).  Wider and
+    // FP64 shapes keep the symmetric form sqrt(lam) + (1/sqrt(lam) -
+    // sqrt(lam)) / (1 + r), whose factors lie in [0.1, 10].
+    constexpr bool kUnitBase = std::is_same<R, float>::value && EPL <= kUnitBaseMaxEpl;
     uint32_t e_xa[EPL];
-    R e_invT[EPL], e_b[EPL], e_d[EPL];
+    R e_invT[EPL], e_b[kUnitBase ? 1 : EPL], e_d[EPL];
     NT e_n[EPL];
     // Gene slots: state, stages, G', k and LDS addresses (publish, prefix end/begin).
     R x[GPL], y[GPL], kk[7][GPL], gG[GPL], gk[GPL];
-    uint32_t g_wa[GPL], g_pe[GPL], g_pb[GPL];
-    int g_id[GPL];
+    uint32_t g_pe[GPL], g_pb[GPL];
 #pragma unroll
     for (int s = 0; s < EPL; ++s) {
-        e_xa[s] = sink; e_invT[s] = 0; e_b[s] = 1; e_d[s] = 0; e_n[s] = O::to_n(1);
+        e_xa[s] = sink; e_invT[s] = 0; e_d[s] = 0; e_n[s] = O::to_n(1);
+        if constexpr (!kUnitBase) e_b[s] = 1;
     }
+    auto base_of = [&](int s) -> R {
+        if constexpr (kUnitBase) return (R)1;
+        else return e_b[s];
+    };
 #pragma unroll
     for (int q = 0; q < GPL; ++q) {
         x[q] = 0; y[q] = 0; gG[q] = 0; gk[q] = 0;
-        g_wa[q] = sink; g_pe[q] = pre_base; g_pb[q] = pre_base; g_id[q] = -1;
+        g_pe[q] = pre_base; g_pb[q] = pre_base;
 #pragma unroll
         for (int l = 0; l < 7; ++l) kk[l][q] = 0;
     }
@@ -235,16 +252,22 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
     int net = 0, kout = 0, nacc = 0, nrej = 0;
     bool fresh = false, last_rej = false;
     double t = 0, h = 0, t_stop = 0;
-    bool exhausted = false;
-    uint64_t popped = 0;  // queue position after this wave's last pop
+    bool exhausted = false;   // queue drained and no claimed index left
+    bool drained = false;     // the shared queue has nothing left to pop
+    uint64_t popped = 0;      // queue position after this wave's last pop
+    // Indices this wave has claimed but not started: [claim_next, claim_end).
+    uint64_t claim_next = 0, claim_end = 0;
     int n_genes = 1;
     double inv_n = 1.0;   // 1 / n_genes of the group's network
+    // Gene slot q of this lane holds gene r + q * lpt; slots past n_genes pad.
+    auto gene_of = [&](int q) { return r + q * lpt; };
+    auto is_real = [&](int q) { return r + q * lpt < n_genes; };
 
     // One right-hand-side evaluation f(yv) for every lane of the wave: no
     // branches, padding slots evaluate factors of exactly 1.
     auto rhs = [&](const R (&yv)[GPL], R (&f)[GPL]) {
 #pragma unroll
-        for (int q = 0; q < GPL; ++q) st(g_wa[q], O::publish(yv[q]));
+        for (int q = 0; q < GPL; ++q) st(pub_base + (uint32_t)q * 64 * SZ, O::publish(yv[q]));
         wave_sync();
         R run = 1;
         // Chunks of up to four independent factors, then their running products.
@@ -254,7 +277,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 if (c0 + j < EPL)
-                    hv[j] = O::hill(ld(e_xa[c0 + j]), e_invT[c0 + j], e_n[c0 + j], e_b[c0 + j], e_d[c0 + j]);
+                    hv[j] = O::hill(ld(e_xa[c0 + j]), e_invT[c0 + j], e_n[c0 + j], base_of(c0 + j), e_d[c0 + j]);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 if (c0 + j < EPL) {
@@ -285,13 +308,13 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
         if (!TS) {
 #pragma unroll
             for (int q = 0; q < GPL; ++q)
-                if (g_id[q] >= 0) xo[g_id[q]] = x[q];
+                if (is_real(q)) xo[gene_of(q)] = x[q];
         } else {
             // Steady before the last output: the remaining outputs hold x_ss.
             for (int k = kout; k < a.n_t; ++k)
 #pragma unroll
                 for (int q = 0; q < GPL; ++q)
-                    if (g_id[q] >= 0) xo[(int64_t)k * N + g_id[q]] = x[q];
+                    if (is_real(q)) xo[(int64_t)k * N + gene_of(q)] = x[q];
         }
         if (r == 0) {
             double* tf = RAC_DF(t_final);
@@ -356,30 +379,42 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
             const float* Tp = RAC_DF(T) + p;
             const float* Lp = RAC_DF(lam) + p;
             const uint8_t* Np = RAC_DF(n) + p;
-            // Only the loads are conditional: padding slots take T = lam = n = 1
-            // and the sink, which the same formulas turn into beta' = 1 and
-            // delta' = 0 (every array element is written on one path, which
-            // keeps the arrays in registers).
+            // Only the loads are conditional: padding slots take T = lam = n = 1,
+            // an inhibiting sign and the sink, which the same formulas turn
+            // into a factor of exactly 1 (every array element is written on
+            // one path, which keeps the arrays in registers).
 #pragma unroll
             for (int s = 0; s < EPL; ++s) {
                 asm volatile("" ::: "memory");
                 const int pk = s < stride ? lane_edge[s] : -1;
                 float Tv = 1.0f, Lv = 1.0f;
                 int nv = 1;
+                bool act = false;
                 uint32_t xa = sink;
                 if (pk >= 0) {
-                    const int e = pk & 0xffff, src = pk >> 16;
+                    const int e = pk & 0x7fff, src = pk >> 16;
+                    act = (pk & 0x8000) != 0;
                     Tv = Tp[e * P];
                     Lv = Lp[e * P];
                     nv = Np[e * P];
                     xa = (wave_elem + (uint32_t)(src * n_groups + g)) * SZ;
                 }
-                const R sl = O::sqrt((R)Lv);
                 e_xa[s] = xa;
-                e_invT[s] = O::edge_t((R)Tv, nv);
-                e_n[s] = O::to_n(nv);
-                e_b[s] = sl;
-                e_d[s] = (R)1 / sl - sl;
+                if constexpr (kUnitBase) {
+                    // Activation: H^S = 1 + (lam - 1) / (1 + (T/x)^n), the
+                    // exponent negated; inhibition: H^S = lam (1 + (1/lam - 1)
+                    // / (1 + (x/T)^n)), the lam folded into the gene below.
+                    const float nn = act ? -(float)nv : (float)nv;
+                    e_n[s] = nn;
+                    e_invT[s] = nn * __builtin_amdgcn_logf(Tv);
+                    e_d[s] = act ? Lv - 1.0f : 1.0f / Lv - 1.0f;
+                } else {
+                    const R sl = O::sqrt((R)Lv);
+                    e_invT[s] = O::edge_t((R)Tv, nv);
+                    e_n[s] = O::to_n(nv);
+                    e_b[s] = sl;
+                    e_d[s] = (R)1 / sl - sl;
+                }
             }
             const float* Gp = RAC_DF(G) + p;
             const float* Kp = RAC_DF(k) + p;
@@ -400,25 +435,33 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
                 if (real) {
                     Gv = (R)Gp[gene * P];
                     kv = (R)Kp[gene * P];
-                    // Fold each row's sqrt(lam) (and, for activation
-                    // over lambda, 1/lam) into the production rate.
+                    // Fold the edge factors' constant parts into the
+                    // production rate: lam per inhibiting edge and, for
+                    // activation over lambda, 1/lam per activating edge
+                    // (or sqrt(lam) and 1/sqrt(lam) in the symmetric form).
                     gf = Gv;
                     for (int e = row_ptr[gene]; e < row_ptr[gene + 1]; ++e) {
-                        const R sl = O::sqrt((R)Lp[e * P]);
-                        gf *= (sign[e] > 0 && c.divide) ? (R)1 / sl : sl;
+                        const R lv = (R)Lp[e * P];
+                        if constexpr (kUnitBase) {
+                            gf *= sign[e] > 0 ? (c.divide ? (R)1 / lv : (R)1) : lv;
+                        } else {
+                            const R sl = O::sqrt(lv);
+                            gf *= (sign[e] > 0 && c.divide) ? (R)1 / sl : sl;
+                        }
                     }
                     row = gene_row[gene];
                     u = (R)icp[gene];
                 }
                 const int rl = row & 0xff, pb = (row >> 8) & 0xff, pe = (row >> 16) & 0xff;
                 const uint32_t rowlane = (uint32_t)(gshift + rl);
-                g_id[q] = real ? gene : -1;
-                g_wa[q] = real ? (wave_elem + (uint32_t)(gene * n_groups + g)) * SZ : sink;
                 g_pb[q] = real ? (wave_elem + 64 * GPL + (uint32_t)pb * 64 + rowlane) * SZ : pre_base;
                 g_pe[q] = real ? (wave_elem + 64 * GPL + (uint32_t)pe * 64 + rowlane) * SZ : pre_base;
                 gG[q] = gf;
                 gk[q] = real ? kv : (R)0;
-                x[q] = c.ic_absolute ? u : u * Gv / kv;
+                // Padding slots hold x = 1 with G = k = 0: their derivative,
+                // error and steady test are exactly 0, 0 and true, and their
+                // error scale atol + rtol is positive.
+                x[q] = real ? (c.ic_absolute ? u : u * Gv / kv) : (R)1;
             }
             t = c.t0;
             t_stop = TS ? a.t_out[a.n_t - 1] : c.t_end;
@@ -475,29 +518,53 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
                         : (uint64_t)a.total;
             // Refill in batches (each refill costs the wave two extra right-hand
             // sides), but take single items once the queue is nearly drained.
-            const bool near_end = popped >= total ||
-                                  total - popped < (uint64_t)gridDim.x * (kBlock / 64) * 64;
+            const uint64_t n_waves = (uint64_t)gridDim.x * (kBlock / 64);
+            const bool near_end = popped >= total || total - popped < n_waves * 64;
             if (nfree > 0 && (nfree >= c.refill_min || busy_lead == 0 || near_end)) {
+                // Serve from this wave's claimed indices first; pop the rest
+                // from the shared queue.  While the queue is long, one pop
+                // claims a whole chunk (one atomic per chunk instead of per
+                // refill); near its end, and in step batches (whose waves
+                // keep no claims between batches), a pop takes exactly what
+                // is needed.
+                const uint64_t local_n = claim_end - claim_next < (uint64_t)nfree ? claim_end - claim_next
+                                                                                 : (uint64_t)nfree;
+                const uint64_t need = (uint64_t)nfree - local_n;
                 unsigned long long base = 0, got = 0;
-                if (lane == 0) {
-                    // One atomic per wave.  In step batches head may run past
-                    // total; the batch's last graph node clamps it back before
-                    // the host appends more, so appended indices are served.
-                    base = atomicAdd(a.counter, (unsigned long long)nfree);
-                    got = base >= total ? 0ull
-                                        : (base + (unsigned long long)nfree <= total ? (unsigned long long)nfree
-                                                                                    : total - base);
+                if (need > 0 && !drained) {
+                    const bool claim = !BOUNDED && total - popped > n_waves * (uint64_t)c.chunk * 2 &&
+                                       popped < total;
+                    const uint64_t want = claim && need < (uint64_t)c.chunk ? (uint64_t)c.chunk : need;
+                    if (lane == 0) {
+                        // One atomic per wave.  In step batches head may run
+                        // past total; the batch's last graph node clamps it
+                        // back before the host appends more, so appended
+                        // indices are served.
+                        base = atomicAdd(a.counter, (unsigned long long)want);
+                        got = base >= total ? 0ull
+                                            : (base + (unsigned long long)want <= total ? (unsigned long long)want
+                                                                                       : total - base);
+                    }
+                    base = __shfl(base, 0);
+                    got = __shfl(got, 0);
+                    popped = base + got;
+                    if (base + want >= total || got < want) drained = true;
                 }
-                base = __shfl(base, 0);
-                got = __shfl(got, 0);
-                popped = base + got;
-                if (base + (unsigned long long)nfree >= total || got < (unsigned long long)nfree)
-                    exhausted = true;
                 if (traj < 0) {
-                    const int rank = __popcll(free_lead & ((1ull << gshift) - 1ull));
-                    const int64_t idx = (int64_t)base + rank;
-                    if ((unsigned long long)rank < got && (uint64_t)idx < total) load_traj(idx);
+                    const uint64_t rank = (uint64_t)__popcll(free_lead & ((1ull << gshift) - 1ull));
+                    if (rank < local_n) {
+                        load_traj((int64_t)(claim_next + rank));
+                    } else if (rank - local_n < (uint64_t)got) {
+                        const uint64_t idx = (uint64_t)base + (rank - local_n);
+                        if (idx < total) load_traj((int64_t)idx);
+                    }
                 }
+                claim_next += local_n;
+                if (got > need) {
+                    claim_next = (uint64_t)base + need;
+                    claim_end = (uint64_t)base + got;
+                }
+                if (drained && claim_next >= claim_end) exhausted = true;
             }
         }
         if (__ballot(traj >= 0) == 0) {
@@ -520,7 +587,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
 #pragma unroll
             for (int q = 0; q < GPL; ++q) {
                 if (fresh) kk[0][q] = kk[1][q];
-                if (g_id[q] >= 0) {
+                if (is_real(q)) {
                     const float xv = (float)x[q], fv = (float)kk[1][q];
                     fin = fin && __builtin_isfinite(xv) && __builtin_isfinite(fv);
                     const float isc = 1.0f / ((float)c.atol + (float)c.rtol * fabsf(xv));
@@ -539,7 +606,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
                 while (kout < a.n_t && a.t_out[kout] <= t) {
 #pragma unroll
                     for (int q = 0; q < GPL; ++q)
-                        if (g_id[q] >= 0) xo[(int64_t)kout * N + g_id[q]] = x[q];
+                        if (is_real(q)) xo[(int64_t)kout * N + gene_of(q)] = x[q];
                     ++kout;
                 }
             }
@@ -552,7 +619,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
             float s2 = 0;
 #pragma unroll
             for (int q = 0; q < GPL; ++q)
-                if (g_id[q] >= 0) {
+                if (is_real(q)) {
                     const float dv = (float)(kk[2][q] - kk[0][q]) /
                                      ((float)c.atol + (float)c.rtol * fabsf((float)x[q]));
                     s2 += dv * dv;
@@ -601,6 +668,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
             clipped = true;
         }
         const R hR = (R)hs;
+        R epart[GPL];  // error combination of k1..k6, formed before the last stage
 #pragma unroll
         for (int st_ = 1; st_ < 7; ++st_) {
 #pragma unroll
@@ -611,6 +679,19 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
                     if (tab_a<M>(st_, l) != 0.0) acc += (R)tab_a<M>(st_, l) * kk[l][q];
                 y[q] = x[q] + hR * acc;
             }
+            if (st_ == 6) {
+                // Summing k1..k6 into the error now (same order as one pass
+                // over k1..k7) frees them during the last right-hand side
+                // unless dense output still needs them.
+#pragma unroll
+                for (int q = 0; q < GPL; ++q) {
+                    R e = (R)tab_e<M>(0) * kk[0][q];
+#pragma unroll
+                    for (int l = 1; l < 6; ++l)
+                        if (tab_e<M>(l) != 0.0) e += (R)tab_e<M>(l) * kk[l][q];
+                    epart[q] = e;
+                }
+            }
             rhs(y, kk[st_]);
         }
         // y now holds the fifth-order solution, kk[6] its derivative.
@@ -618,17 +699,15 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
         bool fin = true;
 #pragma unroll
         for (int q = 0; q < GPL; ++q) {
-            R e = (R)tab_e<M>(0) * kk[0][q];
-#pragma unroll
-            for (int l = 1; l < 7; ++l)
-                if (tab_e<M>(l) != 0.0) e += (R)tab_e<M>(l) * kk[l][q];
+            R e = epart[q];
+            if (tab_e<M>(6) != 0.0) e += (R)tab_e<M>(6) * kk[6][q];
             // Scaled error e_i / (atol + rtol max(|x_i|, |x_new,i|)); the ratio
             // in R, its square accumulated in FP64.
             const R ax = O::abs(x[q]), an = O::abs(y[q]);
             const R sc = (R)c.atol + (R)c.rtol * (ax > an ? ax : an);
-            const double rq = g_id[q] >= 0 ? (double)(hR * e * O::rcp(sc)) : 0.0;
+            const double rq = (double)(hR * e * O::rcp(sc));
             serr += rq * rq;
-            fin = fin && (g_id[q] < 0 || __builtin_isfinite(y[q]));
+            fin = fin && __builtin_isfinite(y[q]);
         }
         // Accept iff the RMS error is <= 1, i.e. its square is; one factor
         // 0.9 err^(-1/5), clamped to [0.2, 10] after an accepted step that did
@@ -661,11 +740,11 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
                                       th * ((R)kTsDense[l][1] + th * ((R)kTsDense[l][2] + th * (R)kTsDense[l][3])));
 #pragma unroll
                     for (int q = 0; q < GPL; ++q) {
-                        if (g_id[q] >= 0) {
+                        if (is_real(q)) {
                             R acc = bt[0] * kk[0][q];
 #pragma unroll
                             for (int l = 1; l < 7; ++l) acc += bt[l] * kk[l][q];
-                            xo[(int64_t)kout * N + g_id[q]] = x[q] + hR * acc;
+                            xo[(int64_t)kout * N + gene_of(q)] = x[q] + hR * acc;
                         }
                     }
                 } else {
@@ -674,7 +753,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
                     const R th1 = (R)1 - th;
 #pragma unroll
                     for (int q = 0; q < GPL; ++q) {
-                        if (g_id[q] >= 0) {
+                        if (is_real(q)) {
                             const R ydiff = y[q] - x[q];
                             const R bspl = hR * kk[0][q] - ydiff;
                             const R c4 = ydiff - hR * kk[6][q] - bspl;
@@ -682,7 +761,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
 #pragma unroll
                             for (int l = 2; l < 7; ++l) c5 += (R)kDense[l] * kk[l][q];
                             c5 *= hR;
-                            xo[(int64_t)kout * N + g_id[q]] =
+                            xo[(int64_t)kout * N + gene_of(q)] =
                                 x[q] + th * (ydiff + th1 * (bspl + th * (c4 + th1 * c5)));
                         }
                     }
@@ -698,7 +777,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
             for (int q = 0; q < GPL; ++q) {
                 x[q] = y[q];
                 kk[0][q] = kk[6][q];
-                steady = steady && (g_id[q] < 0 || is_steady(kk[0][q], gk[q], x[q]));
+                steady = steady && is_steady(kk[0][q], gk[q], x[q]);
             }
         }
         const bool all_steady = group_all(steady);

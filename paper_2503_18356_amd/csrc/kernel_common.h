@@ -22,7 +22,7 @@
 namespace rac {
 
 struct NetDesc {
-    const int32_t* lane_edge;  // [lpt][stride] packed (edge | src << 16), -1 empty
+    const int32_t* lane_edge;  // [lpt][stride] packed (edge | activating << 15 | src << 16), -1 empty
     const int32_t* gene_row;   // [N] packed row lane | begin << 8 | end << 16
     const int32_t* row_ptr;    // [N + 1]
     const int8_t* sign;        // [E]
@@ -45,10 +45,17 @@ struct NetDesc {
     int32_t n_genes, n_edges, n_ic, stride;
 };
 
+// FP32 kernels with at most this many edge slots per lane evaluate each Hill
+// factor as 1 + D / (1 + 2^z), D >= 0; others use the symmetric form with a
+// base term.  The two agree to rounding, not bit for bit.
+constexpr int kUnitBaseMaxEpl = 16;
+
 struct Controls {
     double t0, t_end, rtol, atol, ss_atol, ss_rtol, h0;
     int64_t max_steps;
     int32_t divide, ic_absolute, stop_at_steady, refill_min;
+    int32_t chunk;  // queue indices a wave claims per pop while the queue is long
+    int32_t pad;
 };
 
 // Device-resident queue control of a serving step batch: the kernel pops

@@ -27,7 +27,7 @@ constexpr Shape kShapesF32[] = {
     {4, 1}, {4, 2}, {4, 3}, {4, 4}, {4, 6}, {4, 8}, {8, 1}, {8, 2}, {8, 3}, {8, 4}, {8, 6},
     {8, 8}, {12, 1}, {12, 2}, {12, 3}, {12, 4}, {12, 6}, {12, 8}, {16, 1}, {16, 2}, {16, 3},
     {16, 4}, {16, 6}, {16, 8}, {24, 1}, {24, 2}, {24, 3}, {24, 4}, {24, 6}, {32, 1}, {32, 2},
-    {32, 3}, {7, 3}, {11, 3}};
+    {32, 3}, {7, 3}, {11, 3}, {13, 5}};
 constexpr Shape kShapesF64[] = {
     {4, 1}, {4, 2}, {4, 3}, {4, 4}, {4, 6}, {8, 1}, {8, 2}, {8, 3}, {8, 4}, {12, 1}, {12, 2},
     {12, 3}, {16, 1}, {16, 2}, {7, 3}};
@@ -38,7 +38,8 @@ struct LanePlan {
     int epl = 0;      // edge slots used per lane (max over lanes)
     int stride = 1;   // row stride of lane_edge = max(epl, 1)
     int gpl = 0;      // gene slots used per lane = ceil(N / lpt)
-    // [lpt][epl]: (edge id) | (src gene << 16), or -1 for an empty slot.
+    // [lpt][epl]: (edge id) | (activating << 15) | (src gene << 16), or -1 for
+    // an empty slot (edge ids stay below 2^15).
     std::vector<int32_t> lane_edge;
     // [N]: row lane | (first prefix index << 8) | (end prefix index << 16).
     std::vector<int32_t> gene_row;

@@ -196,6 +196,8 @@ Controls make_controls(const rac_solver_opts* o, int n_groups) {
     c.ic_absolute = o->ic_absolute ? 1 : 0;
     c.stop_at_steady = o->stop_at_steady ? 1 : 0;
     c.refill_min = o->refill_min > 0 ? o->refill_min : std::max(1, n_groups / 4);
+    c.chunk = n_groups;
+    c.pad = 0;
     return c;
 }
 
@@ -459,6 +461,11 @@ rac_status rac_steady_states_batch(const rac_batch_item* items, int32_t n_items,
         jobs.push_back({it.topo, it.params, it.ic, it.n_ic, it.x_out, it.info});
     }
     return run_jobs(jobs, opts, false, nullptr, 0, hip_stream);
+}
+
+int32_t rac_factor_form(int32_t precision, int32_t epl) {
+    if ((precision != RAC_FP32 && precision != RAC_FP64) || epl < 1) return -1;
+    return precision == RAC_FP32 && epl <= rac::kUnitBaseMaxEpl ? 1 : 0;
 }
 
 }  // extern "C"

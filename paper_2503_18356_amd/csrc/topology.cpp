@@ -72,7 +72,7 @@ static LanePlan build_plan(const rac_topology* t, int lpt) {
         for (int i : lane_rows[l]) {
             int begin = s;
             for (int e = t->row_ptr[i]; e < t->row_ptr[i + 1]; ++e) {
-                p.lane_edge[(size_t)l * p.stride + s] = e | (t->src[e] << 16);
+                p.lane_edge[(size_t)l * p.stride + s] = e | (t->sign[e] > 0 ? 0x8000 : 0) | (t->src[e] << 16);
                 ++s;
             }
             p.gene_row[i] = l | (begin << 8) | (s << 16);

@@ -113,6 +113,8 @@ def lib():
         L.rac_lanes_supported.restype = i32
         L.rac_plan_shape.argtypes = [vp, i32, i32, vp, vp]
         L.rac_plan_shape.restype = C.c_int
+        L.rac_factor_form.argtypes = [i32, i32]
+        L.rac_factor_form.restype = i32
         L.rac_sample_params_device.argtypes = [vp, C.POINTER(_Ranges), C.c_uint64, i64, i64, i32,
                                                C.POINTER(_ParamsView), vp, vp]
         L.rac_sample_params_device.restype = C.c_int
@@ -152,6 +154,16 @@ def _check(code: int):
 
 def last_error() -> str:
     return lib().rac_last_error().decode()
+
+
+def factor_form(precision: int, epl: int) -> int:
+    """Hill-factor form of the kernels with this precision and edge-slot count
+    (1: 1 + D / (1 + 2^z); 0: symmetric sqrt(lam) form).  Kernels of one form
+    and lane count give bit-identical results whatever their slot counts."""
+    f = int(lib().rac_factor_form(precision, epl))
+    if f < 0:
+        raise ValueError(f"bad precision {precision} or epl {epl}")
+    return f
 
 
 class Topology:

@@ -196,7 +196,11 @@ class GpuExecutor:
             if not T.lanes_supported(kl, fp32):
                 continue
             ne, ng = T.shape(kl, fp32)
-            if ke >= ne and kg >= ng:
+            # Only classes whose kernels use the same Hill-factor form as the
+            # network's own shape, so that a merged request gives the same
+            # bits as a direct solve at that lane count.
+            same_form = self.rp.factor_form(fp32, ke) == self.rp.factor_form(fp32, ne)
+            if ke >= ne and kg >= ng and same_form:
                 c = self.slot_cost(kl, ke, kg)
                 if c <= self.merge_slack * own and (best is None or c < best[0]):
                     best = (c, key)

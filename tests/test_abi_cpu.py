@@ -161,6 +161,16 @@ def test_lane_choices():
     assert not ts.lanes_supported(3)
 
 
+def test_factor_form_switch_point():
+    # FP32 kernels of up to 16 edge slots use the base-free Hill factor; wider
+    # FP32 and all FP64 kernels the symmetric one.
+    assert [rp.factor_form(rp.FP32, e) for e in (1, 7, 16, 17, 24, 32)] == [1, 1, 1, 0, 0, 0]
+    assert [rp.factor_form(rp.FP64, e) for e in (1, 7, 16)] == [0, 0, 0]
+    for bad in ((rp.FP32, 0), (5, 4)):
+        with pytest.raises(ValueError):
+            rp.factor_form(*bad)
+
+
 def test_default_options_and_server_method_check():
     o = rp.Opts().c()
     assert o.method == rp.DP5 and o.rtol == 1e-6 and o.atol == 1e-9

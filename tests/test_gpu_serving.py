@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests import parity
 from paper_2503_18356_amd import inputs
 from paper_2503_18356_amd import racipe as rp
 from paper_2503_18356_amd.serve import GpuExecutor, Request, Scheduler, poisson_requests
@@ -172,6 +173,7 @@ def test_network_in_a_larger_shape_matches_its_own():
     lanes = T.auto_lanes()
     epl, gpl = T.shape(lanes)
     big = (min(e for e in (4, 8, 12, 16, 24, 32) if e > epl), min(g for g in (1, 2, 3, 4, 6, 8) if g > gpl))
+    assert rp.factor_form(rp.FP32, big[0]) == rp.factor_form(rp.FP32, epl)
     params = rp.sample_params(T, 91, 400, 3).to_device()
     ref = _direct(T, params, lanes)
     try:
@@ -195,6 +197,47 @@ def test_network_in_a_larger_shape_matches_its_own():
         pytest.fail("request did not finish")
     assert torch.equal(out.x, ref.x)
     assert torch.equal(out.n_acc, ref.n_acc) and torch.equal(out.status, ref.status)
+
+
+def _serve_all(srv, T, params, n):
+    out = rp.alloc_result(n, T.n_genes, rp.FP32)
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    srv.submit(T, params, out, stream=stream)
+    counts = np.zeros(1, np.int32)
+    for _ in range(5000):
+        srv.step(stream=stream)
+        srv.done_counts(0, 1, counts, stream=stream)
+        torch.cuda.synchronize()
+        if counts[0] >= n:
+            return out
+    pytest.fail("request did not finish")
+
+
+def test_both_factor_forms_agree_with_the_oracle():
+    # One network solved by kernels of both Hill-factor forms: its own shape
+    # (1 + D / (1 + 2^z)) and a serving shape past the switch point (the
+    # symmetric sqrt(lam) form).  Each meets the parity bar against the oracle.
+    T = rp.Topology.from_inputs(inputs.erdos_renyi(10, 25, 1002))
+    lanes = T.auto_lanes()
+    epl, gpl = T.shape(lanes)
+    wide = 24
+    assert rp.factor_form(rp.FP32, epl) == 1 and rp.factor_form(rp.FP32, wide) == 0
+    n_sets, n_ic, seed = 200, 5, 93
+    params = rp.sample_params(T, seed, n_sets, n_ic).to_device()
+    own = _direct(T, params, lanes)
+    srv = rp.StepServer(rp.Opts(precision=rp.FP32), lanes, wide, gpl, max_requests=4, batch_steps=64)
+    other = _serve_all(srv, T, params, n_sets * n_ic)
+    say(f"own shape {(epl, gpl)} vs {(wide, gpl)} at {lanes} lanes")
+    net = oracle.canonicalize(T.n_genes, *[np.asarray(v) for v in (T.src, T.dst, T.sign)])
+    op = oracle.sample(net, seed, n_sets, n_ic)
+    oo = oracle.Opts(ss_rtol=1e-5)
+    ids = np.arange(0, n_sets * n_ic, 7)
+    ref = oracle.steady_states(net, op, oo, traj_ids=ids, n_threads=8)
+    for name, res in (("unit", own), ("symmetric", other)):
+        rep = parity.compare_steady(net, op, oo, ids, res.x.cpu().numpy()[ids], ref.x, n_ic)
+        say(name, rep)
+        assert rep.ok(), (name, str(rep))
 
 
 def test_scheduler_on_gpu_poisson_stream():
