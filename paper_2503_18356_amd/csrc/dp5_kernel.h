@@ -155,6 +155,13 @@ __device__ __forceinline__ double dpp_mov(double v) {
 // Sum over the aligned group of lpt lanes (a power of two); every lane of
 // the group gets the same bits, since each level adds two equal partial sums
 // in either order.  Called from wave-uniform control flow only.
+// A value every lane of the wave holds, moved to scalar registers.
+__device__ __forceinline__ unsigned long long uniform64(unsigned long long v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 template <typename T>
 __device__ __forceinline__ T group_reduce(T v, int lpt) {
     if (lpt >= 2) v += dpp_mov<kDppXor1>(v);
@@ -175,11 +182,19 @@ enum : int { kRunning = -1 };
 //                               padding gene slots write levels nobody reads)
 //   [64*GPL, 64*(GPL+EPL+1))    running products, index slot * 64 + lane
 //   [64*(GPL+EPL+1), +64)       one sink per lane, read by padding edge slots
+//   [64*(GPL+EPL+2), +128*GPL)  (G', k) of gene slot q of each lane, pair index
+//                               q * 64 + lane (private to the lane: loaded with
+//                               the trajectory, read by every right-hand side)
 // Every address a lane uses is precomputed as an absolute LDS byte offset.
 template <typename R, int EPL, int GPL>
 struct LdsLayout {
-    static constexpr int kSlots = GPL + EPL + 2;
+    static constexpr int kSlots = GPL + EPL + 2 + 2 * GPL;
     static constexpr int kWaveElems = 64 * kSlots;
+};
+
+template <typename R>
+struct alignas(2 * sizeof(R)) RatePair {
+    R G, k;
 };
 
 template <typename R, int EPL, int GPL, bool TS, bool BOUNDED = false, int M = kDP5>
@@ -209,12 +224,21 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
     const uint64_t glow = lpt == 64 ? ~0ull : ((1ull << lpt) - 1);
     // Level of gene slot q: pub_base + q * 64 elements.
     const uint32_t pub_base = (wave_elem + (uint32_t)(r * n_groups + g)) * SZ;
+    // Rates (G', k) of gene slot q: rate_base + q * 128 elements.
+    const uint32_t rate_base = (wave_elem + 64 * (GPL + EPL + 2) + 2 * lane) * SZ;
+    auto rate = [&](int q) -> RatePair<R> {
+        return *reinterpret_cast<const RatePair<R>*>(lb + rate_base + (uint32_t)q * 128 * SZ);
+    };
     const Controls& c = a.c;
 
     st(pre_base, (R)1);  // prefix[0] = 1, never overwritten
     // Padding edge slots read the sink; give it a finite value so that their
     // factor is exactly 1 even for lanes that hold no padding gene slot.
     st(sink, (R)0);
+    // Lanes that never hold a trajectory still evaluate right-hand sides.
+#pragma unroll
+    for (int q = 0; q < GPL; ++q)
+        *reinterpret_cast<RatePair<R>*>(lb + rate_base + (uint32_t)q * 128 * SZ) = RatePair<R>{(R)0, (R)0};
 
     // Edge slots: source address, threshold term (O::edge_t), n, sqrt(lam),
     // 1/sqrt(lam) - sqrt(lam).
@@ -228,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
     R e_invT[EPL], e_b[kUnitBase ? 1 : EPL], e_d[EPL];
     NT e_n[EPL];
     // Gene slots: state, stages, G', k and LDS addresses (publish, prefix end/begin).
-    R x[GPL], y[GPL], kk[7][GPL], gG[GPL], gk[GPL];
+    R x[GPL], y[GPL], kk[7][GPL];
     uint32_t g_pe[GPL], g_pb[GPL];
 #pragma unroll
     for (int s = 0; s < EPL; ++s) {
@@ -241,17 +265,18 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
     };
 #pragma unroll
     for (int q = 0; q < GPL; ++q) {
-        x[q] = 0; y[q] = 0; gG[q] = 0; gk[q] = 0;
+        x[q] = 0; y[q] = 0;
         g_pe[q] = pre_base; g_pb[q] = pre_base;
 #pragma unroll
         for (int l = 0; l < 7; ++l) kk[l][q] = 0;
     }
 
     // Per-group scalars (replicated over the group's lanes).
-    int64_t traj = -1, local = 0;
+    int64_t traj = -1;
     int net = 0, kout = 0, nacc = 0, nrej = 0;
     bool fresh = false, last_rej = false;
-    double t = 0, h = 0, t_stop = 0;
+    double t = 0, h = 0;
+    const double t_stop = TS ? a.t_out[a.n_t - 1] : c.t_end;  // the same for every trajectory
     bool exhausted = false;   // queue drained and no claimed index left
     bool drained = false;     // the shared queue has nothing left to pop
     uint64_t popped = 0;      // queue position after this wave's last pop
@@ -288,7 +313,10 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
         }
         wave_sync();
 #pragma unroll
-        for (int q = 0; q < GPL; ++q) f[q] = gG[q] * (ld(g_pe[q]) * O::rcp(ld(g_pb[q]))) - gk[q] * yv[q];
+        for (int q = 0; q < GPL; ++q) {
+            const RatePair<R> gr = rate(q);
+            f[q] = gr.G * (ld(g_pe[q]) * O::rcp(ld(g_pb[q]))) - gr.k * yv[q];
+        }
     };
 
     auto group_sum = [&](double v) { return group_reduce(v, lpt); };
@@ -304,6 +332,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
         const NetDesc* dp = a.nets ? a.nets + net : nullptr;
 #define RAC_DF(field) (dp ? dp->field : a.net0.field)
         const int N = RAC_DF(n_genes);
+        const int64_t local = traj - RAC_DF(traj_begin);
         R* const xo = (R*)RAC_DF(x_out) + local * (int64_t)(TS ? a.n_t : 1) * N;
         if (!TS) {
 #pragma unroll
@@ -365,7 +394,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
             const NetDesc* dp = a.nets ? a.nets + net : nullptr;
 #define RAC_DF(field) (dp ? dp->field : a.net0.field)
             traj = idx;
-            local = idx - RAC_DF(traj_begin);
+            const int64_t local = idx - RAC_DF(traj_begin);
             const int n_ic = RAC_DF(n_ic);
             int64_t p = (int64_t)((double)local * RAC_DF(inv_n_ic));
             if (p * n_ic > local) --p;
@@ -456,15 +485,14 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
                 const uint32_t rowlane = (uint32_t)(gshift + rl);
                 g_pb[q] = real ? (wave_elem + 64 * GPL + (uint32_t)pb * 64 + rowlane) * SZ : pre_base;
                 g_pe[q] = real ? (wave_elem + 64 * GPL + (uint32_t)pe * 64 + rowlane) * SZ : pre_base;
-                gG[q] = gf;
-                gk[q] = real ? kv : (R)0;
+                *reinterpret_cast<RatePair<R>*>(lb + rate_base + (uint32_t)q * 128 * SZ) =
+                    RatePair<R>{gf, real ? kv : (R)0};
                 // Padding slots hold x = 1 with G = k = 0: their derivative,
                 // error and steady test are exactly 0, 0 and true, and their
                 // error scale atol + rtol is positive.
                 x[q] = real ? (c.ic_absolute ? u : u * Gv / kv) : (R)1;
             }
             t = c.t0;
-            t_stop = TS ? a.t_out[a.n_t - 1] : c.t_end;
             nacc = 0; nrej = 0; kout = 0; last_rej = false;
             fresh = true;
     };
@@ -545,8 +573,8 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
                                             : (base + (unsigned long long)want <= total ? (unsigned long long)want
                                                                                        : total - base);
                     }
-                    base = __shfl(base, 0);
-                    got = __shfl(got, 0);
+                    base = uniform64(__shfl(base, 0));
+                    got = uniform64(__shfl(got, 0));
                     popped = base + got;
                     if (base + want >= total || got < want) drained = true;
                 }
@@ -593,7 +621,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
                     const float isc = 1.0f / ((float)c.atol + (float)c.rtol * fabsf(xv));
                     s0 += (xv * isc) * (xv * isc);
                     s1 += (fv * isc) * (fv * isc);
-                    steady = steady && is_steady(kk[1][q], gk[q], x[q]);
+                    steady = steady && is_steady(kk[1][q], rate(q).k, x[q]);
                 }
             }
             const bool all_fin = group_all(fin);
@@ -602,6 +630,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
             if (TS && fresh) {
                 const NetDesc* dp = a.nets ? a.nets + net : nullptr;
                 const int N = dp ? dp->n_genes : a.net0.n_genes;
+                const int64_t local = traj - (dp ? dp->traj_begin : a.net0.traj_begin);
                 R* xo = (R*)(dp ? dp->x_out : a.net0.x_out) + local * (int64_t)a.n_t * N;
                 while (kout < a.n_t && a.t_out[kout] <= t) {
 #pragma unroll
@@ -728,6 +757,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
         if (TS && accept && kout < a.n_t && a.t_out[kout] <= (clipped ? t_stop : t + hs)) {
             const NetDesc* dp = a.nets ? a.nets + net : nullptr;
             const int N = dp ? dp->n_genes : a.net0.n_genes;
+            const int64_t local = traj - (dp ? dp->traj_begin : a.net0.traj_begin);
             R* xo = (R*)(dp ? dp->x_out : a.net0.x_out) + local * (int64_t)a.n_t * N;
             const double t_new = clipped ? t_stop : t + hs;
             while (kout < a.n_t && a.t_out[kout] <= t_new) {
@@ -777,7 +807,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
             for (int q = 0; q < GPL; ++q) {
                 x[q] = y[q];
                 kk[0][q] = kk[6][q];
-                steady = steady && is_steady(kk[0][q], gk[q], x[q]);
+                steady = steady && is_steady(kk[0][q], rate(q).k, x[q]);
             }
         }
         const bool all_steady = group_all(steady);

@@ -10,7 +10,8 @@
 //   3. owners read prefix[end] / prefix[begin] of their row and form
 //      f_i = G_i' * P_i - k_i * y_i.
 // Step control, the error norm and the steady test are per group; groups
-// that finish are refilled from a device work queue (one atomic per wave).
+// that finish are refilled from a device work queue (each wave claims chunks
+// of queue indices with one atomic per chunk).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,6 +19,7 @@
 #include <cstdint>
 
 #include "rac.h"
+#include "rac_internal.h"
 
 namespace rac {
 
@@ -44,11 +46,6 @@ struct NetDesc {
     double inv_n_ic;           // 1 / n_ic
     int32_t n_genes, n_edges, n_ic, stride;
 };
-
-// FP32 kernels with at most this many edge slots per lane evaluate each Hill
-// factor as 1 + D / (1 + 2^z), D >= 0; others use the symmetric form with a
-// base term.  The two agree to rounding, not bit for bit.
-constexpr int kUnitBaseMaxEpl = 16;
 
 struct Controls {
     double t0, t_end, rtol, atol, ss_atol, ss_rtol, h0;

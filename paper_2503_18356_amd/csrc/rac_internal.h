@@ -23,6 +23,10 @@ constexpr int kWave = 64;
 struct Shape {
     int epl, gpl;
 };
+// FP32 kernels with at most this many edge slots per lane evaluate each Hill
+// factor as 1 + D / (1 + 2^z), D >= 0; others use the symmetric form with a
+// base term.  The two agree to rounding, not bit for bit.
+constexpr int kUnitBaseMaxEpl = 16;
 constexpr Shape kShapesF32[] = {
     {4, 1}, {4, 2}, {4, 3}, {4, 4}, {4, 6}, {4, 8}, {8, 1}, {8, 2}, {8, 3}, {8, 4}, {8, 6},
     {8, 8}, {12, 1}, {12, 2}, {12, 3}, {12, 4}, {12, 6}, {12, 8}, {16, 1}, {16, 2}, {16, 3},

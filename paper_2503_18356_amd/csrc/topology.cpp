@@ -101,8 +101,10 @@ bool plan_fits(const rac_topology* t, int lpt, int precision) {
 // footprint (waves per SIMD).  The constants come from timing the kernel
 // shapes on MI355X; the autotuner measures instead of estimating.
 static double shape_efficiency(const Shape& s, int precision) {
-    const double vgpr = precision == RAC_FP64 ? 70.0 + 10.0 * s.epl + 32.0 * s.gpl
-                                              : 58.0 + 5.0 * s.epl + 17.0 * s.gpl;
+    // Fitted to the compiled kernels' VGPR counts (FP32 edges cost one
+    // register less in the base-free factor form).
+    const double vgpr = precision == RAC_FP64 ? 105.0 + 8.0 * s.epl + 18.0 * s.gpl
+                                              : 55.0 + (s.epl <= kUnitBaseMaxEpl ? 4.0 : 5.0) * s.epl + 12.0 * s.gpl;
     const int waves = vgpr > 256 ? 1 : std::min(8, (int)(512.0 / (8.0 * std::ceil(vgpr / 8.0))));
     static const double eff[] = {0.0, 0.30, 0.54, 0.71, 0.88, 1.0, 1.0, 1.0, 1.0};
     return eff[waves];
