@@ -455,8 +455,8 @@ def bench_serve(args, torch, rp, flops, inputs):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="er10", choices=["er10", "ts", "uneven64", "core22ts", "serve", "ising"])
     ap.add_argument("--n-sets", type=int, default=10000)
     ap.add_argument("--n-ic", type=int, default=100)

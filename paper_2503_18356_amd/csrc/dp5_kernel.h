@@ -141,20 +141,20 @@ __device__ __forceinline__ void wave_sync() {
 // Cross-lane moves inside a row of 16 lanes (DPP): quad butterflies for
 // masks 1 and 2, the half-row and row mirrors pair groups of 4 and 8 lanes.
 enum : int { kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140 };
+// Every pattern used reads a lane of the same row, so no lane takes the
+// bound-control default.
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_mov(double v) {
     const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xf, 0xf, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, true);
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
-// Sum over the aligned group of lpt lanes (a power of two); every lane of
-// the group gets the same bits, since each level adds two equal partial sums
-// in either order.  Called from wave-uniform control flow only.
+
 // A value every lane of the wave holds, moved to scalar registers.
 __device__ __forceinline__ unsigned long long uniform64(unsigned long long v) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -162,14 +162,28 @@ __device__ __forceinline__ unsigned long long uniform64(unsigned long long v) {
     return ((unsigned long long)hi << 32) | lo;
 }
 
+// Sum over the aligned group of lpt lanes (a power of two); every lane of
+// the group gets the same bits, since each level adds two equal partial sums
+// in either order.  Called from wave-uniform control flow only; the levels
+// nest so that a small group tests only the levels it takes plus one.
 template <typename T>
 __device__ __forceinline__ T group_reduce(T v, int lpt) {
-    if (lpt >= 2) v += dpp_mov<kDppXor1>(v);
-    if (lpt >= 4) v += dpp_mov<kDppXor2>(v);
-    if (lpt >= 8) v += dpp_mov<kDppHalfMirror>(v);
-    if (lpt >= 16) v += dpp_mov<kDppMirror>(v);
-    if (lpt >= 32) v += __shfl_xor(v, 16);
-    if (lpt >= 64) v += __shfl_xor(v, 32);
+    if (lpt >= 2) {
+        v += dpp_mov<kDppXor1>(v);
+        if (lpt >= 4) {
+            v += dpp_mov<kDppXor2>(v);
+            if (lpt >= 8) {
+                v += dpp_mov<kDppHalfMirror>(v);
+                if (lpt >= 16) {
+                    v += dpp_mov<kDppMirror>(v);
+                    if (lpt >= 32) {
+                        v += __shfl_xor(v, 16);
+                        if (lpt >= 64) v += __shfl_xor(v, 32);
+                    }
+                }
+            }
+        }
+    }
     return v;
 }
 
