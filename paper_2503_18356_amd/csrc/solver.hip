@@ -340,16 +340,19 @@ rac_status run_jobs(std::vector<Job>& jobs, const rac_solver_opts* o, bool ts,
         }
         return RAC_OK;
     }
-    // Several launches: largest first, spread over the caller's stream and the
-    // library's side streams (forked from and joined back into the caller's
-    // stream), so that the tail of one persistent launch, when few of its
-    // trajectories remain, is filled by the waves of another.
+    // Several launches, spread over the caller's stream and the library's
+    // side streams (forked from and joined back into the caller's stream), so
+    // that the tail of one persistent launch, when few of its trajectories
+    // remain, is filled by the waves of another.  Largest estimated work
+    // first, each onto the stream with the least work so far (longest
+    // processing time first); a launch's work is its trajectories times the
+    // per-step cost of its lane count and shape.
     std::vector<std::pair<double, const std::tuple<int, int, int>*>> order;
     for (auto& kv : groups) {
-        double work = 0;
-        for (const Job& j : kv.second)
-            work += (double)j.params.n_sets * j.n_ic * (j.topo->n_edges + j.topo->n_genes + 1);
-        order.push_back({work, &kv.first});
+        double n_traj = 0;
+        for (const Job& j : kv.second) n_traj += (double)j.params.n_sets * j.n_ic;
+        const Shape s{std::get<1>(kv.first), std::get<2>(kv.first)};
+        order.push_back({n_traj * shape_cost(std::get<0>(kv.first), s, o->precision), &kv.first});
     }
     std::sort(order.begin(), order.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
     int dev = 0;
@@ -361,9 +364,12 @@ rac_status run_jobs(std::vector<Job>& jobs, const rac_solver_opts* o, bool ts,
     RAC_HIP(hipEventRecord(fork, main), "hipEventRecord");
     for (hipStream_t sd : side) RAC_HIP(hipStreamWaitEvent(sd, fork, 0), "hipStreamWaitEvent");
     rac_status st = RAC_OK;
+    std::vector<double> load(side.size() + 1, 0.0);  // [0]: the caller's stream
     for (size_t k = 0; k < order.size() && st == RAC_OK; ++k) {
         const auto& key = *order[k].second;
-        hipStream_t sk = k % (side.size() + 1) == 0 ? main : side[k % (side.size() + 1) - 1];
+        const size_t i = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[i] += order[k].first;
+        hipStream_t sk = i == 0 ? main : side[i - 1];
         st = launch_group(groups[key], std::get<0>(key), o, ts, host_t_out, n_t, sk);
     }
     // Join: the caller's stream waits for everything enqueued on the side streams.

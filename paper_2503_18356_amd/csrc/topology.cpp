@@ -110,6 +110,10 @@ static double shape_efficiency(const Shape& s, int precision) {
     return eff[waves];
 }
 
+double shape_cost(int lpt, const Shape& s, int precision) {
+    return lpt * (14.0 * s.epl + 25.0 * s.gpl + 40.0) / shape_efficiency(s, precision);
+}
+
 int auto_lanes(const rac_topology* t, int precision) {
     int best = 0;
     double best_cost = 0;
@@ -118,7 +122,7 @@ int auto_lanes(const rac_topology* t, int precision) {
         const LanePlan* p = get_plan(t, lpt);
         // Padded slots are evaluated too, so cost the compiled shape.
         const Shape s = pick_shape(std::max(p->epl, 1), p->gpl, precision);
-        const double cost = lpt * (14.0 * s.epl + 25.0 * s.gpl + 40.0) / shape_efficiency(s, precision);
+        const double cost = shape_cost(lpt, s, precision);
         if (best == 0 || cost < best_cost) {
             best = lpt;
             best_cost = cost;
