@@ -189,21 +189,35 @@ __device__ __forceinline__ T group_reduce(T v, int lpt) {
 
 enum : int { kRunning = -1 };
 
-// LDS use per wave, in elements of R:
-//   [0, 64*GPL)                 source levels, index gene * n_groups + group
-//                               (gene slot q of lane r holds gene r + q * lpt, so
-//                               its level sits 64 elements after slot q - 1's;
-//                               padding gene slots write levels nobody reads)
-//   [64*GPL, 64*(GPL+EPL+1))    running products, index slot * 64 + lane
-//   [64*(GPL+EPL+1), +64)       one sink per lane, read by padding edge slots
-//   [64*(GPL+EPL+2), +128*GPL)  (G', k) of gene slot q of each lane, pair index
+// LDS use per wave, in elements of R (P = kPubStride * GPL):
+//   [0, P)                      source levels: gene i = r + q * lpt (slot q of
+//                               group lane r) of group g at q * kPubStride +
+//                               r * S + g, S = kPubStride / lpt (1 at 64 lanes);
+//                               padding gene slots write levels nobody reads
+//   [P, P + 64*(EPL+1))         running products, index slot * 64 + lane
+//   [P + 64*(EPL+1), +64)       one sink per lane, read by padding edge slots
+//   [P + 64*(EPL+2), +128*GPL)  (G', k) of gene slot q of each lane, pair index
 //                               q * 64 + lane (private to the lane: loaded with
 //                               the trajectory, read by every right-hand side)
+//   then 16 bytes per lane      the group's network record (1/N, N, network
+//                               index), private to the lane, read once a step
 // Every address a lane uses is precomputed as an absolute LDS byte offset.
+// The level stride S = 96 / lpt spreads the sources that the lanes of a half
+// wave read in one edge slot over the 32 LDS banks: group g's copies of one
+// gene are consecutive, and genes whose index differs by 1, 2 or 3 modulo 4
+// start at banks 24, 16 or 8 apart (S = 24 at 4 lanes; the levels written by
+// one half wave fall on 32 distinct banks).
+constexpr int kPubStride = 96;
 template <typename R, int EPL, int GPL>
 struct LdsLayout {
-    static constexpr int kSlots = GPL + EPL + 2 + 2 * GPL;
-    static constexpr int kWaveElems = 64 * kSlots;
+    static constexpr int kPub = kPubStride * GPL;
+    static constexpr int kRec = kPub + 64 * (EPL + 2 + 2 * GPL);  // start of the network records
+    static constexpr int kWaveElems = kRec + 64 * 16 / (int)sizeof(R);
+};
+
+struct alignas(16) GroupRec {
+    double inv_n;  // 1 / N of the group's network
+    int32_t n_genes, net;
 };
 
 template <typename R>
@@ -226,8 +240,8 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
 
     const int lane = threadIdx.x & 63;
     const uint32_t wave_elem = (threadIdx.x >> 6) * Lay::kWaveElems;
-    const uint32_t pre_base = (wave_elem + 64 * GPL + lane) * SZ;        // prefix[0] of this lane
-    const uint32_t sink = (wave_elem + 64 * (GPL + EPL + 1) + lane) * SZ;
+    const uint32_t pre_base = (wave_elem + Lay::kPub + lane) * SZ;        // prefix[0] of this lane
+    const uint32_t sink = (wave_elem + Lay::kPub + 64 * (EPL + 1) + lane) * SZ;
 
     const int lpt = a.lpt;
     const int sh = __builtin_ctz(lpt);
@@ -236,10 +250,14 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
     const int r = lane & (lpt - 1);   // lane within the group
     const int gshift = g * lpt;
     const uint64_t glow = lpt == 64 ? ~0ull : ((1ull << lpt) - 1);
-    // Level of gene slot q: pub_base + q * 64 elements.
-    const uint32_t pub_base = (wave_elem + (uint32_t)(r * n_groups + g)) * SZ;
+    // Level of gene slot q: pub_base + q * kPubStride elements.
+    const int pub_s = __builtin_amdgcn_readfirstlane(lpt == 64 ? 1 : kPubStride / lpt);
+    auto level_index = [&](int gene) {  // element index of a gene's level in this group
+        return (uint32_t)((gene >> sh) * kPubStride + (gene & (lpt - 1)) * pub_s + g);
+    };
+    const uint32_t pub_base = (wave_elem + (uint32_t)(r * pub_s + g)) * SZ;
     // Rates (G', k) of gene slot q: rate_base + q * 128 elements.
-    const uint32_t rate_base = (wave_elem + 64 * (GPL + EPL + 2) + 2 * lane) * SZ;
+    const uint32_t rate_base = (wave_elem + Lay::kPub + 64 * (EPL + 2) + 2 * lane) * SZ;
     auto rate = [&](int q) -> RatePair<R> {
         return *reinterpret_cast<const RatePair<R>*>(lb + rate_base + (uint32_t)q * 128 * SZ);
     };
@@ -287,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
 
     // Per-group scalars (replicated over the group's lanes).
     int64_t traj = -1;
-    int net = 0, kout = 0, nacc = 0, nrej = 0;
+    int kout = 0, nacc = 0, nrej = 0;
     bool fresh = false, last_rej = false;
     double t = 0, h = 0;
     const double t_stop = TS ? a.t_out[a.n_t - 1] : c.t_end;  // the same for every trajectory
@@ -296,17 +314,18 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
     uint64_t popped = 0;      // queue position after this wave's last pop
     // Indices this wave has claimed but not started: [claim_next, claim_end).
     uint64_t claim_next = 0, claim_end = 0;
-    int n_genes = 1;
-    double inv_n = 1.0;   // 1 / n_genes of the group's network
-    // Gene slot q of this lane holds gene r + q * lpt; slots past n_genes pad.
+    // The group's network (index, N, 1/N), kept in LDS rather than registers.
+    GroupRec* const rec = reinterpret_cast<GroupRec*>(lb + (wave_elem + Lay::kRec) * SZ + 16 * lane);
+    *rec = GroupRec{1.0, 1, 0};
+    // Gene slot q of this lane holds gene r + q * lpt; slots past N pad.
     auto gene_of = [&](int q) { return r + q * lpt; };
-    auto is_real = [&](int q) { return r + q * lpt < n_genes; };
+    auto is_real = [&](int q) { return r + q * lpt < rec->n_genes; };
 
     // One right-hand-side evaluation f(yv) for every lane of the wave: no
     // branches, padding slots evaluate factors of exactly 1.
     auto rhs = [&](const R (&yv)[GPL], R (&f)[GPL]) {
 #pragma unroll
-        for (int q = 0; q < GPL; ++q) st(pub_base + (uint32_t)q * 64 * SZ, O::publish(yv[q]));
+        for (int q = 0; q < GPL; ++q) st(pub_base + (uint32_t)q * kPubStride * SZ, O::publish(yv[q]));
         wave_sync();
         R run = 1;
         // Chunks of up to four independent factors, then their running products.
@@ -343,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
 
     // Write the end-of-trajectory record and free the group.
     auto finish = [&](int status) {
-        const NetDesc* dp = a.nets ? a.nets + net : nullptr;
+        const NetDesc* dp = a.nets ? a.nets + rec->net : nullptr;
 #define RAC_DF(field) (dp ? dp->field : a.net0.field)
         const int N = RAC_DF(n_genes);
         const int64_t local = traj - RAC_DF(traj_begin);
@@ -390,7 +409,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
     // its network, load and derive its parameters, set x0.
     auto load_traj = [&](int64_t idx) {
             // Which network: binary search over first queue indices.
-            net = 0;
+            int net = 0;
             if (a.nets) {
                 int lo = 0, hi = (BOUNDED ? __hip_atomic_load(&a.ctl->n_nets, __ATOMIC_RELAXED,
                                                                __HIP_MEMORY_SCOPE_AGENT)
@@ -415,8 +434,8 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
             if ((p + 1) * n_ic <= local) ++p;
             const int ci = (int)(local - p * n_ic);
             const int64_t P = RAC_DF(n_sets);
-            n_genes = RAC_DF(n_genes);
-            inv_n = 1.0 / n_genes;
+            const int n_genes = RAC_DF(n_genes);
+            *rec = GroupRec{1.0 / n_genes, n_genes, net};
             const int stride = RAC_DF(stride);
             const int32_t* lane_edge = RAC_DF(lane_edge) + r * stride;
             const float* Tp = RAC_DF(T) + p;
@@ -440,7 +459,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
                     Tv = Tp[e * P];
                     Lv = Lp[e * P];
                     nv = Np[e * P];
-                    xa = (wave_elem + (uint32_t)(src * n_groups + g)) * SZ;
+                    xa = (wave_elem + level_index(src)) * SZ;
                 }
                 e_xa[s] = xa;
                 if constexpr (kUnitBase) {
@@ -497,8 +516,8 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
                 }
                 const int rl = row & 0xff, pb = (row >> 8) & 0xff, pe = (row >> 16) & 0xff;
                 const uint32_t rowlane = (uint32_t)(gshift + rl);
-                g_pb[q] = real ? (wave_elem + 64 * GPL + (uint32_t)pb * 64 + rowlane) * SZ : pre_base;
-                g_pe[q] = real ? (wave_elem + 64 * GPL + (uint32_t)pe * 64 + rowlane) * SZ : pre_base;
+                g_pb[q] = real ? (wave_elem + Lay::kPub + (uint32_t)pb * 64 + rowlane) * SZ : pre_base;
+                g_pe[q] = real ? (wave_elem + Lay::kPub + (uint32_t)pe * 64 + rowlane) * SZ : pre_base;
                 *reinterpret_cast<RatePair<R>*>(lb + rate_base + (uint32_t)q * 128 * SZ) =
                     RatePair<R>{gf, real ? kv : (R)0};
                 // Padding slots hold x = 1 with G = k = 0: their derivative,
@@ -640,9 +659,10 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
             }
             const bool all_fin = group_all(fin);
             const bool all_steady = group_all(steady);
+            const int n_genes = rec->n_genes;
             const float d0 = sqrtf(group_sumf(s0) / n_genes), d1 = sqrtf(group_sumf(s1) / n_genes);
             if (TS && fresh) {
-                const NetDesc* dp = a.nets ? a.nets + net : nullptr;
+                const NetDesc* dp = a.nets ? a.nets + rec->net : nullptr;
                 const int N = dp ? dp->n_genes : a.net0.n_genes;
                 const int64_t local = traj - (dp ? dp->traj_begin : a.net0.traj_begin);
                 R* xo = (R*)(dp ? dp->x_out : a.net0.x_out) + local * (int64_t)a.n_t * N;
@@ -755,7 +775,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
         // Accept iff the RMS error is <= 1, i.e. its square is; one factor
         // 0.9 err^(-1/5), clamped to [0.2, 10] after an accepted step that did
         // not follow a rejection and to [0.2, 1] otherwise.
-        const double err2 = group_sum(serr) * inv_n;
+        const double err2 = group_sum(serr) * rec->inv_n;
         const bool all_fin = group_all(fin);  // collective: evaluated by every lane
         const bool accept = running && all_fin && err2 <= 1.0;
         const bool err_ok = __builtin_isfinite(err2);
@@ -769,7 +789,7 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
         }
         // Dense output for every output time inside the accepted step.
         if (TS && accept && kout < a.n_t && a.t_out[kout] <= (clipped ? t_stop : t + hs)) {
-            const NetDesc* dp = a.nets ? a.nets + net : nullptr;
+            const NetDesc* dp = a.nets ? a.nets + rec->net : nullptr;
             const int N = dp ? dp->n_genes : a.net0.n_genes;
             const int64_t local = traj - (dp ? dp->traj_begin : a.net0.traj_begin);
             R* xo = (R*)(dp ? dp->x_out : a.net0.x_out) + local * (int64_t)a.n_t * N;
