@@ -246,7 +246,8 @@ def bench_er10(args, torch, rp, flops, inputs):
         post = lambda: rp.analyse_steady_states(T, dp, out, 64, 2, 1 << 16, stream=stream)
         post()
         w_pp, lat_pp = timed(post, 5, stream, torch)
-        nb = flops.postproc_bytes(T.n_genes, args.n_sets, args.n_ic, n_bins=64, capacity=1 << 16)
+        nb = flops.postproc_bytes(T.n_genes, args.n_sets, args.n_ic, n_bins=64,
+                                  capacity=rp.state_table_size(n_traj, T.n_genes, 2, 1 << 16))
         rec["postproc"] = {
             "ms": float(lat_pp.mean()), "algorithmic_bytes": nb,
             "achieved_GBps": nb / (lat_pp.mean() * 1e-3) / 1e9, "peak_GBps": PEAK_HBM / 1e9,

@@ -14,6 +14,7 @@
 #include <string>
 
 #include "rac.h"
+#include "fastdiv.h"
 #include "rac_internal.h"
 
 namespace rac {
@@ -44,15 +45,52 @@ __device__ __forceinline__ int bin_of(float y, int n_bins) {
     return b < n_bins - 1 ? b : n_bins - 1;
 }
 
+// Element e of x[rows][N]: row e / N, gene e % N, parameter set row / (n_t n_ic).
+// Index arithmetic in 32 bits when the element count allows it.  With x and y
+// 16-byte aligned (VEC) each thread takes four consecutive elements (16-byte
+// loads and stores) and the last one the ragged tail; otherwise one element.
+template <bool WIDE>
+__device__ __forceinline__ float normalized(float xv, int64_t e, int N, int64_t P, int64_t rows_per_set,
+                                            const FastDiv& by_n, const FastDiv& by_set,
+                                            const float* __restrict__ G, const float* __restrict__ k) {
+    int64_t r, p;
+    if (WIDE) {
+        r = e / N;
+        p = r / rows_per_set;
+    } else {
+        r = fastdiv((uint32_t)e, by_n);
+        p = fastdiv((uint32_t)r, by_set);
+    }
+    const int i = (int)(e - r * N);
+    return __fdiv_rn(__fmul_rn(xv, k[i * P + p]), G[i * P + p]);
+}
+
+template <bool WIDE, bool VEC>
 __global__ void normalize_kernel(const float* __restrict__ x, float* __restrict__ y, int64_t n_elem,
-                                 int N, int64_t P, int n_ic, int n_t, const float* __restrict__ G,
-                                 const float* __restrict__ k) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_elem;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = e / N;
-        const int i = (int)(e - r * N);
-        const int64_t p = r / n_t / n_ic;
-        y[e] = __fdiv_rn(__fmul_rn(x[e], k[i * P + p]), G[i * P + p]);
+                                 int N, int64_t P, int64_t rows_per_set, FastDiv by_n, FastDiv by_set,
+                                 const float* __restrict__ G, const float* __restrict__ k) {
+    if (!VEC) {
+        for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_elem;
+             e += (int64_t)gridDim.x * blockDim.x)
+            y[e] = normalized<WIDE>(x[e], e, N, P, rows_per_set, by_n, by_set, G, k);
+        return;
+    }
+    const int64_t n4 = n_elem >> 2;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q <= n4;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = q << 2;
+        if (q < n4) {
+            const float4 xv = reinterpret_cast<const float4*>(x)[q];
+            float4 yv;
+            yv.x = normalized<WIDE>(xv.x, e, N, P, rows_per_set, by_n, by_set, G, k);
+            yv.y = normalized<WIDE>(xv.y, e + 1, N, P, rows_per_set, by_n, by_set, G, k);
+            yv.z = normalized<WIDE>(xv.z, e + 2, N, P, rows_per_set, by_n, by_set, G, k);
+            yv.w = normalized<WIDE>(xv.w, e + 3, N, P, rows_per_set, by_n, by_set, G, k);
+            reinterpret_cast<float4*>(y)[q] = yv;
+        } else {
+            for (int64_t t = e; t < n_elem; ++t)
+                y[t] = normalized<WIDE>(x[t], t, N, P, rows_per_set, by_n, by_set, G, k);
+        }
     }
 }
 
@@ -63,22 +101,49 @@ __global__ void fill_kernel(T* a, int64_t n, T v) {
         a[e] = v;
 }
 
-// Block-local LDS histogram, then one atomic per bin into the global counts.
-__global__ void histogram_kernel(const float* __restrict__ y, int64_t n_rows, int N,
-                                 const int8_t* __restrict__ status, int n_bins,
-                                 unsigned long long* __restrict__ hist) {
-    __shared__ unsigned int h[kMaxBins];
-    for (int b = threadIdx.x; b < n_bins; b += blockDim.x) h[b] = 0;
+// LDS histogram per wave (values cluster in few bins, so one shared copy per
+// workgroup serialises its atomics four times as much), summed per bin at
+// the end with one global atomic per bin and workgroup.
+template <bool WIDE, bool VEC>
+__global__ __launch_bounds__(kThreads) void histogram_kernel(const float* __restrict__ y, int64_t n_rows, int N,
+                                                             FastDiv by_n, const int8_t* __restrict__ status,
+                                                             int n_bins, unsigned long long* __restrict__ hist) {
+    __shared__ unsigned int h[kThreads / 64][kMaxBins];
+    for (int b = threadIdx.x; b < n_bins; b += blockDim.x)
+        for (int w = 0; w < kThreads / 64; ++w) h[w][b] = 0;
     __syncthreads();
+    unsigned int* const mine = h[threadIdx.x >> 6];
     const int64_t n_elem = n_rows * N;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_elem;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        if (status && status[e / N] != RAC_CONVERGED) continue;
-        atomicAdd(&h[bin_of(y[e], n_bins)], 1u);
+    auto add = [&](float v, int64_t e) {
+        if (status && status[WIDE ? e / N : (int64_t)fastdiv((uint32_t)e, by_n)] != RAC_CONVERGED) return;
+        atomicAdd(&mine[bin_of(v, n_bins)], 1u);
+    };
+    // Four consecutive elements per thread (16-byte loads; y 16-byte aligned),
+    // the ragged tail last; otherwise one element per thread.
+    const int64_t n4 = VEC ? n_elem >> 2 : -1;
+    if (!VEC)
+        for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_elem;
+             e += (int64_t)gridDim.x * blockDim.x)
+            add(y[e], e);
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q <= n4;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = q << 2;
+        if (q < n4) {
+            const float4 v = reinterpret_cast<const float4*>(y)[q];
+            add(v.x, e);
+            add(v.y, e + 1);
+            add(v.z, e + 2);
+            add(v.w, e + 3);
+        } else {
+            for (int64_t t = e; t < n_elem; ++t) add(y[t], t);
+        }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < n_bins; b += blockDim.x)
-        if (h[b]) atomicAdd(&hist[b], (unsigned long long)h[b]);
+    for (int b = threadIdx.x; b < n_bins; b += blockDim.x) {
+        unsigned int c = 0;
+        for (int w = 0; w < kThreads / 64; ++w) c += h[w][b];
+        if (c) atomicAdd(&hist[b], (unsigned long long)c);
+    }
 }
 
 // Exhaustive multi-level Otsu over threshold tuples 0 < t1 < ... < t_{L-1} < B:
@@ -177,13 +242,71 @@ __global__ void discretize_kernel(const float* __restrict__ y, int64_t n_rows, i
     }
 }
 
-// One workgroup per parameter set: bitonic sort of its n_ic codes in LDS,
-// then the distinct codes (NO_STATE excluded) in ascending order.
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// One wave per parameter set, for n_ic <= 128: the set's codes sit two per
+// lane (indices lane and lane + 64, NO_STATE past n_ic), a bitonic network
+// over the 128 keys runs in registers (cross-lane pairs by shuffles, the
+// stride-64 pairs inside a lane), first occurrences are flagged against the
+// preceding key and their output positions come from lane-masked popcounts
+// of the ballots.
+__global__ __launch_bounds__(kThreads) void multistability_wave(const uint64_t* __restrict__ codes, int64_t n_sets,
+                                                                int n_ic, int* __restrict__ n_states,
+                                                                uint64_t* __restrict__ states) {
+    const int lane = threadIdx.x & 63;
+    const int64_t p = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    if (p >= n_sets) return;  // uniform over the wave
+    const uint64_t* c = codes + p * n_ic;
+    uint64_t a = lane < n_ic ? c[lane] : kNoState;
+    uint64_t b = lane + 64 < n_ic ? c[lane + 64] : kNoState;
+    for (int size = 2; size <= 128; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            if (stride == 64) {  // size 128: pairs (lane, lane + 64), ascending
+                const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+                a = lo;
+                b = hi;
+            } else {
+                const uint64_t pa = shfl_u64(a, lane ^ stride), pb = shfl_u64(b, lane ^ stride);
+                const bool lower = (lane & stride) == 0;
+                const bool min_a = lower == ((lane & size) == 0);
+                const bool min_b = lower == (((lane + 64) & size) == 0);
+                a = (min_a == (pa < a)) ? pa : a;
+                b = (min_b == (pb < b)) ? pb : b;
+            }
+        }
+    }
+    // Every lane takes part in every shuffle (a shuffle reads the source lane's
+    // register, which must be active); the selects come afterwards.
+    const int up1 = lane == 0 ? 0 : lane - 1;
+    const uint64_t prev_a = shfl_u64(a, up1);
+    const uint64_t last_a = shfl_u64(a, 63);
+    const uint64_t sb = shfl_u64(b, up1);
+    const uint64_t prev_b = lane == 0 ? last_a : sb;
+    const bool fa = a != kNoState && (lane == 0 || a != prev_a);
+    const bool fb = b != kNoState && b != prev_b;
+    const uint64_t ma = __ballot(fa), mb = __ballot(fb);
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int na = __popcll(ma), total = na + __popcll(mb);
+    uint64_t* out = states + p * n_ic;
+    if (fa) out[__popcll(ma & below)] = a;
+    if (fb) out[na + __popcll(mb & below)] = b;
+    for (int i = total + lane; i < n_ic; i += 64) out[i] = kNoState;
+    if (lane == 0) n_states[p] = total;
+}
+
+// One workgroup per parameter set, for larger n_ic: bitonic sort of its n_ic
+// codes in LDS (n_pow2 keys, dynamic shared memory), then the distinct codes
+// (NO_STATE excluded) in ascending order, placed by a block-wide scan of the
+// per-thread counts.
 __global__ __launch_bounds__(kThreads) void multistability_kernel(const uint64_t* __restrict__ codes, int n_ic,
                                                                   int n_pow2, int* __restrict__ n_states,
                                                                   uint64_t* __restrict__ states) {
-    __shared__ uint64_t key[kMaxStatesPerSet];
-    __shared__ int cnt[kThreads + 1];
+    extern __shared__ uint64_t key[];
+    __shared__ int wsum[kThreads / 64];
     const int64_t p = blockIdx.x;
     const uint64_t* c = codes + p * n_ic;
     for (int i = threadIdx.x; i < n_pow2; i += blockDim.x) key[i] = i < n_ic ? c[i] : kNoState;
@@ -211,20 +334,27 @@ __global__ __launch_bounds__(kThreads) void multistability_kernel(const uint64_t
     int mine = 0;
     for (int i = beg; i < end; ++i)
         mine += key[i] != kNoState && (i == 0 || key[i] != key[i - 1]);
-    cnt[threadIdx.x + 1] = mine;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        cnt[0] = 0;
-        for (int t = 1; t <= (int)blockDim.x; ++t) cnt[t] += cnt[t - 1];
-        n_states[p] = cnt[blockDim.x];
+    // Exclusive scan of the counts: inside each wave by shuffles, then over
+    // the wave totals.
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int incl = mine;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(incl, d);
+        if (lane >= d) incl += t;
     }
+    if (lane == 63) wsum[wave] = incl;
     __syncthreads();
+    int before = 0, total = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        if (w < wave) before += wsum[w];
+        total += wsum[w];
+    }
     uint64_t* out = states + p * n_ic;
-    int pos = cnt[threadIdx.x];
+    int pos = before + incl - mine;
     for (int i = beg; i < end; ++i)
         if (key[i] != kNoState && (i == 0 || key[i] != key[i - 1])) out[pos++] = key[i];
-    const int total = cnt[blockDim.x];
     for (int i = total + threadIdx.x; i < n_ic; i += blockDim.x) out[i] = kNoState;
+    if (threadIdx.x == 0) n_states[p] = total;
 }
 
 // 64-bit finaliser (splitmix64) as the hash of a state code.
@@ -289,6 +419,20 @@ __global__ __launch_bounds__(kThreads) void insert_kernel(const uint64_t* __rest
         if (lk[i] != kNoState) global_insert(lk[i], lc[i], keys, counts, mask, overflow);
 }
 
+// Clears the hash table (keys NO_STATE, counts 0), the unique counter and
+// overflow flag, and the caller's output arrays, in one pass.
+__global__ void clear_tables(unsigned long long* tk, unsigned long long* tc, unsigned long long* flags,
+                             uint64_t* out_keys, int64_t* out_counts, int64_t cap) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < cap;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        tk[e] = kNoState;
+        tc[e] = 0;
+        out_keys[e] = kNoState;
+        out_counts[e] = 0;
+        if (e < 2) flags[e] = 0;
+    }
+}
+
 __global__ void compact_kernel(const unsigned long long* keys, const unsigned long long* counts, int64_t cap,
                                uint64_t* out_keys, int64_t* out_counts, unsigned long long* n_unique) {
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < cap;
@@ -300,25 +444,43 @@ __global__ void compact_kernel(const unsigned long long* keys, const unsigned lo
     }
 }
 
-// Bitonic sorting network over n (a power of two) (key, count) pairs,
-// ascending by key.  Passes with stride < kTile run inside one LDS tile of
-// kTile pairs (bitonic_tile: every size up to kTile in the first call, then
-// the short strides of each larger size); longer strides are global passes.
+// Bitonic sorting network over the compacted (key, count) pairs, ascending
+// by key.  The compacted entries fill [0, n_unique) and every later entry
+// holds the largest key, so only the first m = n_unique rounded up to a
+// power of two entries need sorting: stages of sizes above m would merge a
+// sorted head with a constant tail and change nothing, and the kernels read
+// m from the device and skip them (the launches stay fixed, so nothing waits
+// for the count on the host).  Passes with stride < kTile run inside one LDS
+// tile (bitonic_tile: every size up to the tile in the first call, then the
+// short strides of each larger size); longer strides are global passes.
 constexpr int kTile = 2048;
 
-__global__ __launch_bounds__(kThreads) void bitonic_tile(uint64_t* keys, int64_t* vals, int64_t n,
-                                                         int64_t size_lo, int64_t size_hi) {
+__device__ __forceinline__ int64_t sort_extent(const unsigned long long* n_unique) {
+    int64_t m = 1;
+    while ((unsigned long long)m < *n_unique) m <<= 1;
+    return m;
+}
+
+// tile = min(n, kTile) pairs per workgroup.
+__global__ __launch_bounds__(kThreads) void bitonic_tile(uint64_t* keys, int64_t* vals, int64_t tile,
+                                                         int64_t size_lo, int64_t size_hi,
+                                                         const unsigned long long* n_unique) {
     __shared__ uint64_t k[kTile];
     __shared__ int64_t v[kTile];
-    const int64_t base = (int64_t)blockIdx.x * kTile;
-    for (int i = threadIdx.x; i < kTile; i += blockDim.x) {
+    const int64_t m = sort_extent(n_unique);
+    const int64_t base = (int64_t)blockIdx.x * tile;
+    if (base >= m || m < 2) return;
+    const int lim = (int)(m - base < tile ? m - base : tile);  // a power of two
+    if (size_hi > m) size_hi = m;
+    if (size_lo > size_hi) return;
+    for (int i = threadIdx.x; i < lim; i += blockDim.x) {
         k[i] = keys[base + i];
         v[i] = vals[base + i];
     }
     __syncthreads();
     for (int64_t size = size_lo; size <= size_hi; size <<= 1) {
-        for (int64_t stride = (size < kTile ? size : kTile) >> 1; stride > 0; stride >>= 1) {
-            for (int i = threadIdx.x; i < kTile; i += blockDim.x) {
+        for (int64_t stride = (size < lim ? size : lim) >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < lim; i += blockDim.x) {
                 const int j = i ^ (int)stride;
                 if (j > i) {
                     const bool up = ((base + i) & size) == 0;
@@ -335,14 +497,17 @@ __global__ __launch_bounds__(kThreads) void bitonic_tile(uint64_t* keys, int64_t
             __syncthreads();
         }
     }
-    for (int i = threadIdx.x; i < kTile; i += blockDim.x) {
+    for (int i = threadIdx.x; i < lim; i += blockDim.x) {
         keys[base + i] = k[i];
         vals[base + i] = v[i];
     }
 }
 
-__global__ void bitonic_pass(uint64_t* keys, int64_t* vals, int64_t n, int64_t size, int64_t stride) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+__global__ void bitonic_pass(uint64_t* keys, int64_t* vals, int64_t size, int64_t stride,
+                             const unsigned long long* n_unique) {
+    const int64_t m = sort_extent(n_unique);
+    if (size > m) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t j = i ^ stride;
         if (j > i) {
@@ -388,8 +553,16 @@ rac_status rac_normalize(const rac_topology* topo, const rac_params_view* p, int
     const int64_t n_elem = p->n_sets * (int64_t)n_ic * n_t * N;
     if (n_elem == 0) return RAC_OK;
     hipStream_t s = (hipStream_t)hip_stream;
-    hipLaunchKernelGGL(normalize_kernel, dim3(grid_for(n_elem)), dim3(kThreads), 0, s, dev_x, dev_y, n_elem, N,
-                       (int64_t)p->n_sets, (int)n_ic, (int)n_t, p->G, p->k);
+    const int64_t rows_per_set = (int64_t)n_ic * n_t;
+    const bool vec = (((uintptr_t)dev_x | (uintptr_t)dev_y) & 15) == 0;
+    const dim3 grid(grid_for(vec ? n_elem / 4 + 1 : n_elem));
+    const bool narrow = n_elem <= 0xffffffffLL;
+    const FastDiv by_n = narrow ? make_fastdiv((uint32_t)N) : FastDiv{1, 0, 0};
+    const FastDiv by_set = narrow ? make_fastdiv((uint32_t)rows_per_set) : FastDiv{1, 0, 0};
+    auto kern = narrow ? (vec ? normalize_kernel<false, true> : normalize_kernel<false, false>)
+                       : (vec ? normalize_kernel<true, true> : normalize_kernel<true, false>);
+    hipLaunchKernelGGL(kern, grid, dim3(kThreads), 0, s, dev_x, dev_y, n_elem, N, (int64_t)p->n_sets, rows_per_set,
+                       by_n, by_set, p->G, p->k);
     RAC_PP(hipGetLastError(), "rac_normalize: launch");
     return RAC_OK;
 }
@@ -410,8 +583,15 @@ rac_status rac_level_thresholds(const float* dev_y, int64_t n_rows, int32_t n_ge
                        (unsigned long long*)dev_hist, (int64_t)n_bins, 0ull);
     RAC_PP(hipGetLastError(), "rac_level_thresholds: clear");
     if (n_rows > 0) {
-        hipLaunchKernelGGL(histogram_kernel, dim3(grid_for(n_rows * n_genes, kThreads * 16)), dim3(kThreads), 0, s,
-                           dev_y, n_rows, (int)n_genes, dev_status, (int)n_bins, (unsigned long long*)dev_hist);
+        const int64_t n_elem = n_rows * n_genes;
+        const bool vec = ((uintptr_t)dev_y & 15) == 0;
+        const dim3 grid(grid_for(vec ? n_elem / 4 + 1 : n_elem, kThreads * 4));
+        const bool narrow = n_elem <= 0xffffffffLL;
+        auto kern = narrow ? (vec ? histogram_kernel<false, true> : histogram_kernel<false, false>)
+                           : (vec ? histogram_kernel<true, true> : histogram_kernel<true, false>);
+        hipLaunchKernelGGL(kern, grid, dim3(kThreads), 0, s, dev_y, n_rows, (int)n_genes,
+                           narrow ? make_fastdiv((uint32_t)n_genes) : FastDiv{1, 0, 0}, dev_status, (int)n_bins,
+                           (unsigned long long*)dev_hist);
         RAC_PP(hipGetLastError(), "rac_level_thresholds: histogram");
     }
     hipLaunchKernelGGL(otsu_kernel, dim3(1), dim3(1024), 0, s, (const unsigned long long*)dev_hist, (int)n_bins,
@@ -451,8 +631,15 @@ rac_status rac_multistability(const uint64_t* dev_codes, int64_t n_sets, int32_t
     if (n_sets == 0) return RAC_OK;
     int n_pow2 = 1;
     while (n_pow2 < n_ic) n_pow2 <<= 1;
-    hipLaunchKernelGGL(multistability_kernel, dim3((unsigned)n_sets), dim3(kThreads), 0, (hipStream_t)hip_stream,
-                       dev_codes, (int)n_ic, n_pow2, dev_n_states, dev_states);
+    if (n_pow2 <= 128) {
+        const int64_t per = kThreads / 64;
+        hipLaunchKernelGGL(multistability_wave, dim3((unsigned)((n_sets + per - 1) / per)), dim3(kThreads), 0,
+                           (hipStream_t)hip_stream, dev_codes, n_sets, (int)n_ic, dev_n_states, dev_states);
+    } else {
+        hipLaunchKernelGGL(multistability_kernel, dim3((unsigned)n_sets), dim3(kThreads),
+                           (unsigned)(n_pow2 * sizeof(uint64_t)), (hipStream_t)hip_stream, dev_codes, (int)n_ic,
+                           n_pow2, dev_n_states, dev_states);
+    }
     RAC_PP(hipGetLastError(), "rac_multistability: launch");
     return RAC_OK;
 }
@@ -474,31 +661,24 @@ rac_status rac_state_counts(const uint64_t* dev_codes, int64_t n_rows, int64_t c
     auto* nu = (unsigned long long*)(ws + (size_t)capacity * 16);
     int* ovf = (int*)(nu + 1);
     const int g = grid_for(capacity);
-    hipLaunchKernelGGL(fill_kernel<unsigned long long>, dim3(g), dim3(kThreads), 0, s, tk, capacity,
-                       (unsigned long long)kNoState);
-    hipLaunchKernelGGL(fill_kernel<unsigned long long>, dim3(g), dim3(kThreads), 0, s, tc, capacity, 0ull);
-    hipLaunchKernelGGL(fill_kernel<unsigned long long>, dim3(1), dim3(64), 0, s, nu, (int64_t)2, 0ull);
-    hipLaunchKernelGGL(fill_kernel<uint64_t>, dim3(g), dim3(kThreads), 0, s, dev_keys, capacity, kNoState);
-    hipLaunchKernelGGL(fill_kernel<int64_t>, dim3(g), dim3(kThreads), 0, s, dev_counts, capacity, (int64_t)0);
+    hipLaunchKernelGGL(clear_tables, dim3(g), dim3(kThreads), 0, s, tk, tc, nu, dev_keys, dev_counts, capacity);
     if (n_rows > 0)
         hipLaunchKernelGGL(insert_kernel, dim3(std::min(grid_for(n_rows), 1024)), dim3(kThreads), 0, s, dev_codes,
                            n_rows, tk, tc, (uint64_t)(capacity - 1), ovf);
     hipLaunchKernelGGL(compact_kernel, dim3(g), dim3(kThreads), 0, s, tk, tc, capacity, dev_keys, dev_counts, nu);
     if (capacity <= kTile) {
-        for (int64_t size = 2; size <= capacity; size <<= 1)
-            for (int64_t stride = size >> 1; stride > 0; stride >>= 1)
-                hipLaunchKernelGGL(bitonic_pass, dim3(g), dim3(kThreads), 0, s, dev_keys, dev_counts, capacity,
-                                   size, stride);
+        hipLaunchKernelGGL(bitonic_tile, dim3(1), dim3(kThreads), 0, s, dev_keys, dev_counts, capacity,
+                           (int64_t)2, capacity, nu);
     } else {
         const int tiles = (int)(capacity / kTile);
-        hipLaunchKernelGGL(bitonic_tile, dim3(tiles), dim3(kThreads), 0, s, dev_keys, dev_counts, capacity,
-                           (int64_t)2, (int64_t)kTile);
+        hipLaunchKernelGGL(bitonic_tile, dim3(tiles), dim3(kThreads), 0, s, dev_keys, dev_counts, (int64_t)kTile,
+                           (int64_t)2, (int64_t)kTile, nu);
         for (int64_t size = 2 * kTile; size <= capacity; size <<= 1) {
             for (int64_t stride = size >> 1; stride >= kTile; stride >>= 1)
-                hipLaunchKernelGGL(bitonic_pass, dim3(g), dim3(kThreads), 0, s, dev_keys, dev_counts, capacity,
-                                   size, stride);
-            hipLaunchKernelGGL(bitonic_tile, dim3(tiles), dim3(kThreads), 0, s, dev_keys, dev_counts, capacity,
-                               size, size);
+                hipLaunchKernelGGL(bitonic_pass, dim3(g), dim3(kThreads), 0, s, dev_keys, dev_counts, size, stride,
+                                   nu);
+            hipLaunchKernelGGL(bitonic_tile, dim3(tiles), dim3(kThreads), 0, s, dev_keys, dev_counts, (int64_t)kTile,
+                               size, size, nu);
         }
     }
     hipLaunchKernelGGL(finish_counts_kernel, dim3(1), dim3(64), 0, s, nu, ovf, dev_n_unique);

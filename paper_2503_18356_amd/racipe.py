@@ -542,17 +542,30 @@ def state_counts(codes, capacity: int = 1 << 16, stream=None):
     return keys, counts, nu
 
 
+def state_table_size(n_rows: int, n_genes: int, n_levels: int, capacity: int = 1 << 16) -> int:
+    """The state-frequency table analyse_steady_states allocates: no more
+    distinct states can occur than rows or than n_levels^N codes, so the
+    smallest power of two (at least 2) holding that many, capped at capacity."""
+    bound = min(n_rows, n_levels ** n_genes)
+    cap = 2
+    while cap < bound and cap < capacity:
+        cap <<= 1
+    return min(cap, capacity)
+
+
 def analyse_steady_states(topo: Topology, params: DeviceParams, result: Result, n_bins: int = 64,
                           n_levels: int = 2, capacity: int = 1 << 16, stream=None) -> dict:
     """The whole chain on a steady-state result, all on the device: normalised
     states, histogram and thresholds, levels and state codes, multistability
-    per parameter set and global state frequencies."""
+    per parameter set and global state frequencies (in a table of
+    state_table_size(rows, N, n_levels, capacity) entries)."""
     N = topo.n_genes
     y = normalize(topo, params, result.x, 1, stream=stream)
     hist, thr = level_thresholds(y, N, result.status, n_bins, n_levels, stream=stream)
     lv, cd = discretize(y, N, thr, result.status, n_bins, n_levels, stream=stream)
     n_states, states = multistability(cd, params.n_sets, params.n_ic, stream=stream)
-    keys, counts, nu = state_counts(cd, capacity, stream=stream)
+    cap = state_table_size(params.n_sets * params.n_ic, N, n_levels, capacity)
+    keys, counts, nu = state_counts(cd, cap, stream=stream)
     return dict(y=y, hist=hist, thresholds=thr, levels=lv, codes=cd, n_states=n_states,
                 states=states, keys=keys, counts=counts, n_unique=nu)
 

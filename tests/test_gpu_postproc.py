@@ -81,7 +81,7 @@ def test_chain_on_integrated_states(topo, levels, bins):
         "multistability histogram", np.bincount(o["n_states"]).tolist())
 
 
-@pytest.mark.parametrize("n_ic", [1, 3, 1000, 4096])
+@pytest.mark.parametrize("n_ic", [1, 3, 64, 128, 129, 1000, 4096])
 def test_chain_on_synthetic_states(n_ic):
     # Random levels with excluded rows, four levels, ragged set sizes.
     rng = np.random.default_rng(n_ic)
