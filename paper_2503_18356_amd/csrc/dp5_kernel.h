@@ -90,9 +90,11 @@ struct Ops<float> {
     __device__ static float to_n(int n) { return (float)n; }
     // Sources publish log2 of their level once per evaluation and edges keep
     // n log2 T, so an edge costs one fma, one exp2 and one reciprocal:
-    //   H^S / sqrt(lam) = beta' + delta' / (1 + 2^(n log2 x - n log2 T)),
-    //   beta' = sqrt(lam), delta' = 1/sqrt(lam) - sqrt(lam).
-    // x = 0 publishes -inf, giving r = 0 and H^S = 1.
+    //   factor = b + d / (1 + 2^(n log2 x - n log2 T)),
+    // with (b, d) = (sqrt(lam), 1/sqrt(lam) - sqrt(lam)) in the symmetric
+    // form, or b = 1, d = D >= 0 and, for activation, n and n log2 T negated
+    // in the base-free form (the kernel body picks the form per shape).
+    // x = 0 publishes -inf, giving the limit H^S = 1 in both forms.
     __device__ static float publish(float v) { return __builtin_amdgcn_logf(v > 0.0f ? v : 0.0f); }
     __device__ static float edge_t(float T, int n) { return (float)n * __builtin_amdgcn_logf(T); }
     __device__ static float hill(float lx, float nlT, float n, float b, float d) {

@@ -4,7 +4,7 @@
 // Each lane owns ceil(N / L) genes (their DP5 state lives in its VGPRs) and a
 // balanced set of whole in-edge rows (their per-trajectory edge parameters
 // live in its VGPRs).  One right-hand-side evaluation is
-//   1. owners publish max(y_i, 0) to LDS,
+//   1. owners publish their level max(y_i, 0) (FP32: its log2) to LDS,
 //   2. every lane walks its edge slots: read the source level from LDS,
 //      evaluate the shifted Hill factor, keep a running product in LDS,
 //   3. owners read prefix[end] / prefix[begin] of their row and form
