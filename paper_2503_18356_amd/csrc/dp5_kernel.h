@@ -190,6 +190,10 @@ __device__ __forceinline__ T group_reduce(T v, int lpt) {
 }
 
 enum : int { kRunning = -1 };
+// Steps after which a trajectory counts as long for wave priority (a little
+// above the typical count of a Table 1 steady-state solve; priority rises
+// again at four times this).
+constexpr int kLongSteps = 100;
 
 // LDS use per wave, in elements of R (P = kPubStride * GPL):
 //   [0, P)                      source levels: gene i = r + q * lpt (slot q of
@@ -629,6 +633,18 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
                 }
                 if (drained && claim_next >= claim_end) exhausted = true;
             }
+        }
+        // Waves that hold an unusually long trajectory (oscillating parameter
+        // sets run to t_end in several times the typical step count) issue
+        // ahead of the others, so that a long trajectory started late in the
+        // queue does not run on alone after every other wave has finished;
+        // the work is the same, only its order changes.  Re-evaluated every
+        // eighth iteration.
+        if ((iter & 7) == 0) {
+            const int steps = nacc + nrej;
+            if (__ballot(traj >= 0 && steps >= kLongSteps) == 0) __builtin_amdgcn_s_setprio(0);
+            else if (__ballot(traj >= 0 && steps >= 4 * kLongSteps) == 0) __builtin_amdgcn_s_setprio(1);
+            else __builtin_amdgcn_s_setprio(3);
         }
         if (__ballot(traj >= 0) == 0) {
             if (exhausted) {
