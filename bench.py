@@ -227,6 +227,20 @@ def bench_er10(args, torch, rp, flops, inputs):
         "steps_per_solve": float((nacc + nrej).mean()),
         "host_sampling_s": t_sample,
     })
+    if not args.no_ceilings:
+        # Secondary ceilings measured on this device (unpacked FP32 FMA, the
+        # transcendentals, FP64 FMA), beside the published peaks.
+        c = rp.valu_ceilings()
+        rec["measured_ceilings"] = {
+            "fp32_fma_tflops": 2 * c["fp32_fma"] / 1e12,
+            "v_exp_f32_tops": c["v_exp_f32"] / 1e12, "v_log_f32_tops": c["v_log_f32"] / 1e12,
+            "v_rcp_f32_tops": c["v_rcp_f32"] / 1e12, "fp64_fma_tflops": 2 * c["fp64_fma"] / 1e12,
+            "fp32_fma_literal_tflops": 2 * c["fp32_fma_literal"] / 1e12,
+            "what": "sustained rates of one-operation kernels built like the solver kernels (no packed "
+                    "FP32), all lanes of the device; fp32_fma takes its operands from registers "
+                    "(v_fma_f32, as the solver does), fp32_fma_literal has a literal multiplier "
+                    "(v_fmamk_f32)"}
+        rec["roofline"]["frac_of_measured_fp32_fma"] = achieved / (2 * c["fp32_fma"])
     if not args.no_plain:
         o64 = rp.Opts(precision=rp.FP64, ss_rtol=1e-5, lanes_per_traj=args.lanes)
         out64 = rp.alloc_result(n_traj, T.n_genes, rp.FP64, device=dev)
@@ -471,6 +485,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-stable-rate", type=float, default=100.0)
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle trajectories (0 = auto)")
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip the VALU ceiling microbenchmarks (FP32 FMA, transcendentals, FP64 FMA)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy, whose FETCH_SIZE/WRITE_SIZE "
                          "counters scale the kernel's HBM traffic figures")

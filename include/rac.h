@@ -456,6 +456,17 @@ int32_t rac_lanes_supported(const rac_topology* topo, int32_t precision, int32_t
 rac_status rac_plan_shape(const rac_topology* topo, int32_t precision, int32_t lanes, int32_t* epl,
                           int32_t* gpl);
 
+/* Measurement support, not part of the method: the sustained lane-operation
+ * rates (operations per second summed over all lanes) of the current device
+ * for, in this order, FP32 FMA with register operands (v_fma_f32),
+ * v_exp_f32, v_log_f32, v_rcp_f32, FP64 FMA and FP32 FMA with a literal
+ * multiplier (v_fmamk_f32), written to lane_ops_per_s[0..min(n, 6)) (entries
+ * past 6 are set to 0).  Synchronous: allocates a scratch buffer and a
+ * stream of its own, runs six short kernels compiled like the solver kernels
+ * (no packed FP32), and returns when they are timed.  EINVAL for a NULL
+ * pointer or n < 1; EDEVICE or ENOMEM when the device calls fail. */
+rac_status rac_valu_ceilings(double* lane_ops_per_s, int32_t n);
+
 /* Which algebraic form of the Hill factor (Eq. 2) kernels of a precision and
  * edge-slot count use: 1 for 1 + D / (1 + 2^z) with D >= 0 and the constant
  * lam (inhibition) or 1/lam (activation over lambda) folded into the

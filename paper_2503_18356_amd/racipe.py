@@ -115,6 +115,8 @@ def lib():
         L.rac_plan_shape.restype = C.c_int
         L.rac_factor_form.argtypes = [i32, i32]
         L.rac_factor_form.restype = i32
+        L.rac_valu_ceilings.argtypes = [vp, i32]
+        L.rac_valu_ceilings.restype = C.c_int
         L.rac_sample_params_device.argtypes = [vp, C.POINTER(_Ranges), C.c_uint64, i64, i64, i32,
                                                C.POINTER(_ParamsView), vp, vp]
         L.rac_sample_params_device.restype = C.c_int
@@ -154,6 +156,18 @@ def _check(code: int):
 
 def last_error() -> str:
     return lib().rac_last_error().decode()
+
+
+CEILING_NAMES = ("fp32_fma", "v_exp_f32", "v_log_f32", "v_rcp_f32", "fp64_fma", "fp32_fma_literal")
+
+
+def valu_ceilings() -> dict:
+    """Measured sustained lane-operation rates (per second, all lanes) of the
+    current device for FP32 FMA (register operands), v_exp/v_log/v_rcp, FP64
+    FMA and FP32 FMA with a literal multiplier."""
+    out = (C.c_double * len(CEILING_NAMES))()
+    _check(lib().rac_valu_ceilings(out, len(CEILING_NAMES)))
+    return dict(zip(CEILING_NAMES, list(out)))
 
 
 def factor_form(precision: int, epl: int) -> int:

@@ -171,6 +171,13 @@ def test_factor_form_switch_point():
             rp.factor_form(*bad)
 
 
+def test_valu_ceilings_rejects_bad_arguments_before_touching_the_device():
+    lib = rp.lib()
+    assert lib.rac_valu_ceilings(None, 5) == rp.EINVAL
+    out = (C.c_double * 1)()
+    assert lib.rac_valu_ceilings(out, 0) == rp.EINVAL
+
+
 def test_default_options_and_server_method_check():
     o = rp.Opts().c()
     assert o.method == rp.DP5 and o.rtol == 1e-6 and o.atol == 1e-9
