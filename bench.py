@@ -36,6 +36,7 @@ PEAK_FP32 = 157.3e12   # MI355X FP32 vector (published; needs packed FP32)
 # FP32 FMA issue without packed instructions, which these kernels are built
 # without: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz.
 PEAK_FP32_UNPACKED = 78.6e12
+PEAK_FP64 = 78.6e12     # MI355X FP64 vector (published)
 PEAK_HBM = 8.0e12
 
 
@@ -94,10 +95,14 @@ def grow(run, n, n_max, target_s):
         n = int(n * min(8.0, 1.1 * target_s / max(w, 1e-3)))
 
 
-def cpu_oracle(topo, seed, n_sets, n_ic, n_pilot, opts_kw=None, t_out=None, target_s=12.0):
+def cpu_oracle(topo, seed, n_sets, n_ic, n_pilot, opts_kw=None, t_out=None, target_s=12.0,
+               gpu_steps=None):
     """The FP64 oracle on the host's cores over a seeded random sample of the
     workload's trajectories, grown from n_pilot until one sample takes about
-    target_s seconds (capped at the whole workload)."""
+    target_s seconds (capped at the whole workload), then one thread on a
+    slice of that sample.  With gpu_steps (the GPU's accepted + rejected step
+    counts per trajectory) it also reports their ratio to the oracle's on the
+    sample."""
     import oracle
     net = oracle.canonicalize(topo.n_genes, topo.src, topo.dst, topo.sign)
     op = oracle.sample(net, seed, n_sets, n_ic)
@@ -106,19 +111,42 @@ def cpu_oracle(topo, seed, n_sets, n_ic, n_pilot, opts_kw=None, t_out=None, targ
     o = oracle.Opts(**(opts_kw or {"ss_rtol": 1e-5}))
     rng = np.random.default_rng(0)
 
-    def run(n):
+    last = {}
+
+    def run(n, n_threads=threads):
         ids = np.sort(rng.choice(n_traj, min(n, n_traj), replace=False))
         c0 = time.perf_counter()
         if t_out is None:
-            oracle.steady_states(net, op, o, traj_ids=ids, n_threads=threads)
+            r = oracle.steady_states(net, op, o, traj_ids=ids, n_threads=n_threads)
         else:
-            oracle.time_series(net, op, t_out, o, traj_ids=ids, n_threads=threads)
+            r = oracle.time_series(net, op, t_out, o, traj_ids=ids, n_threads=n_threads)
+        last.update(ids=ids, res=r)
         return ids.size, time.perf_counter() - c0
 
     n1, cw = grow(run, n_pilot, n_traj, target_s)
-    return {"value": n1 / cw, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n1} seeded random trajectories of the same workload, FP64 DP5(4), "
-                      f"{threads} threads, {cw:.1f} s wall"}
+    rec = {"value": n1 / cw, "unit": "solves/s", "cores": threads, "kind": "oracle",
+           "sample": f"{n1} seeded random trajectories of the same workload, FP64 DP5(4), "
+                     f"{threads} threads, {cw:.1f} s wall",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    if gpu_steps is not None:
+        r, ids = last["res"], last["ids"]
+        rec["steps_gpu_over_oracle"] = float(np.asarray(gpu_steps)[ids].sum()
+                                             / max(1, int((r.n_acc.astype(np.int64) + r.n_rej).sum())))
+    k1, w1 = run(max(1, n1 // (4 * threads)), 1)
+    rec["single_thread"] = {"value": k1 / w1, "unit": "solves/s",
+                            "sample": f"{k1} seeded random trajectories, {w1:.1f} s wall"}
+    return rec
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_oracle_multi(nets, n_pilot, target_s=12.0):
@@ -248,10 +276,15 @@ def bench_er10(args, torch, rp, flops, inputs):
         s64()
         w64, _ = timed(s64, 1, stream, torch)
         v64 = solved(rp, out64.status) / w64
+        steps64 = out64.n_acc.cpu().numpy().astype(np.int64) + out64.n_rej.cpu().numpy()
+        fl64 = flops.credited(T.n_genes, hp.n, args.n_ic, steps64) / w64
         rec["plain_fp64"] = {"value": v64, "unit": "solves/s", "ms_per_step": w64 * 1e3,
                              "what": "FP64 state and RHS, same kernel family, same steady criterion",
-                             "steps_per_solve": float((out64.n_acc.cpu().numpy().astype(np.int64)
-                                                       + out64.n_rej.cpu().numpy()).mean())}
+                             "steps_per_solve": float(steps64.mean()),
+                             "credited_fp64_tflops": fl64 / 1e12,
+                             "frac_of_fp64_peak": fl64 / PEAK_FP64}
+        if "measured_ceilings" in rec:
+            rec["plain_fp64"]["frac_of_measured_fp64_fma"] = fl64 / (rec["measured_ceilings"]["fp64_fma_tflops"] * 1e12)
         rec["speedup_fp32_vs_fp64"] = value / v64
         del out64
     if not args.no_plain:
@@ -286,7 +319,8 @@ def bench_er10(args, torch, rp, flops, inputs):
         rec["latency_ms"] = {"p50": rec["serving"]["p50_ms"], "p99": rec["serving"]["p99_ms"],
                              "what": "serving request latency at the stated offered rate"}
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_oracle(topo, 2002, args.n_sets, args.n_ic, args.cpu_sample or 20000)
+        rec["cpu_baseline"] = cpu_oracle(topo, 2002, args.n_sets, args.n_ic, args.cpu_sample or 20000,
+                                          gpu_steps=nacc + nrej)
     return rec
 
 
