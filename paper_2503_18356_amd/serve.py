@@ -159,7 +159,14 @@ class GpuExecutor:
     memory, then reads the counts the previous iteration copied (waiting on
     its event), so the GPU already holds the next batch while the host
     admits and retires requests.  A request is seen finished one batch after
-    its last trajectory ends."""
+    its last trajectory ends.
+
+    A step server's request table has ``max_requests`` entries and is never
+    reused, so a class whose newest server is full opens another one (a
+    generation); an older generation is destroyed once all its requests are
+    seen finished and the copies and batches enqueued before that have
+    completed.  A class under continuous load therefore runs indefinitely
+    with at most a few generations alive."""
 
     def __init__(self, opts=None, batch_steps: int = 256, max_requests: int = 65536,
                  device="cuda", keep_results: bool = True, merge_slack: float = 2.0,
@@ -176,8 +183,9 @@ class GpuExecutor:
         self.merge_slack = merge_slack
         self.streams = [torch.cuda.Stream(device=device) for _ in range(max(1, n_streams))]
         self.classes: dict[tuple, dict] = {}
-        self.pending = None  # (event, [(class, lo, hi, buffer)]) of the last poll
+        self.pending = None  # (events, [(generation, lo, hi, buffer)]) of the last poll
         self.polls = 0
+        self.retired: list[tuple[int, dict]] = []  # (poll number, drained generation)
 
     @staticmethod
     def slot_cost(lanes: int, epl: int, gpl: int) -> float:
@@ -207,47 +215,66 @@ class GpuExecutor:
         if best is not None:
             return best[1], self.classes[best[1]]
         key = (lanes, epl, gpl)
+        self.classes[key] = {"stream": self.streams[len(self.classes) % len(self.streams)],
+                             "generations": []}
+        return key, self.classes[key]
+
+    def _generation(self, key, cl) -> dict:
+        """The class's newest step server with a free request-table entry."""
+        gens = cl["generations"]
+        if gens and gens[-1]["server"].n_requests < self.max_requests:
+            return gens[-1]
+        lanes, epl, gpl = key
         srv = self.rp.StepServer(self.opts, lanes, epl, gpl, self.max_requests, self.batch_steps)
         bufs = [self.torch.zeros(self.max_requests, dtype=self.torch.int32, pin_memory=True)
                 for _ in range(2)]
-        self.classes[key] = {"server": srv, "stream": self.streams[len(self.classes) % len(self.streams)],
-                             "active": {}, "bufs": bufs, "counts": [b.numpy() for b in bufs]}
-        return key, self.classes[key]
+        gen = {"server": srv, "stream": cl["stream"], "active": {}, "bufs": bufs,
+               "counts": [b.numpy() for b in bufs]}
+        gens.append(gen)
+        return gen
 
     def start(self, req: Request):
         rp = self.rp
         T = rp.Topology.from_inputs(req.topo)
         key, cl = self._class(T)
+        gen = self._generation(key, cl)
         stream = cl["stream"]
         with self.torch.cuda.stream(stream):
             params = rp.alloc_params(T, req.n_sets, req.n_ic, device=self.device)
             rp.sample_params_device(T, req.seed, req.n_sets, req.n_ic, out=params, stream=stream)
             res = rp.alloc_result(req.n_traj, T.n_genes, rp.FP32, device=self.device)
-        srv_rid = cl["server"].submit(T, params, res, stream=stream)
+        srv_rid = gen["server"].submit(T, params, res, stream=stream)
         req.handle = {"class": key, "srv_rid": srv_rid, "T": T, "params": params}
         req.result = res
-        cl["active"][srv_rid] = req
+        gen["active"][srv_rid] = req
+
+    def generations(self) -> int:
+        """Step servers currently alive over all classes."""
+        return sum(len(cl["generations"]) for cl in self.classes.values())
 
     def step(self):
         for cl in self.classes.values():
-            if cl["active"]:
-                cl["server"].step(stream=cl["stream"])
+            for gen in cl["generations"]:
+                if gen["active"]:
+                    gen["server"].step(stream=gen["stream"])
 
     def finished(self) -> list[int]:
         torch = self.torch
         # Enqueue this iteration's counts copies (after the batches just
         # launched) and record one event behind them on every stream used.
         which = self.polls % 2
+        poll = self.polls
         self.polls += 1
         polled = []
         for cl in self.classes.values():
-            act = cl["active"]
-            if act:
-                lo, hi = min(act), max(act) + 1
-                cl["server"].done_counts(lo, hi - lo, cl["counts"][which], stream=cl["stream"])
-                polled.append((cl, lo, hi, which))
+            for gen in cl["generations"]:
+                act = gen["active"]
+                if act:
+                    lo, hi = min(act), max(act) + 1
+                    gen["server"].done_counts(lo, hi - lo, gen["counts"][which], stream=gen["stream"])
+                    polled.append((gen, lo, hi, which))
         events = []
-        for st in {id(cl["stream"]): cl["stream"] for cl, *_ in polled}.values():
+        for st in {id(gen["stream"]): gen["stream"] for gen, *_ in polled}.values():
             ev = torch.cuda.Event()
             ev.record(st)
             events.append(ev)
@@ -257,15 +284,28 @@ class GpuExecutor:
         # Read what the previous iteration copied.
         for ev in prev[0]:
             ev.synchronize()
+        # Generations drained before the previous poll: everything enqueued
+        # on them (their last batch and counts copy) preceded its events.
+        while self.retired and self.retired[0][0] < poll:
+            self.retired.pop(0)
         out = []
-        for cl, lo, hi, w in prev[1]:
-            act = cl["active"]
-            cnt = cl["counts"][w]
+        for gen, lo, hi, w in prev[1]:
+            act = gen["active"]
+            cnt = gen["counts"][w]
             for srv_rid in range(lo, hi):
                 req = act.get(srv_rid)
                 if req is not None and cnt[srv_rid - lo] >= req.n_traj:
                     out.append(req.rid)
                     del act[srv_rid]
+        # A full generation with nothing left in flight leaves its class; it
+        # is destroyed after the events of this poll have completed.
+        for cl in self.classes.values():
+            gens = cl["generations"]
+            keep = [g for g in gens[:-1] if g["active"]] + gens[-1:]
+            for g in gens[:-1]:
+                if not g["active"]:
+                    self.retired.append((poll, g))
+            cl["generations"] = keep
         return out
 
     def release(self, req: Request):

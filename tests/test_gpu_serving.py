@@ -265,3 +265,33 @@ def test_scheduler_on_gpu_poisson_stream():
     gk = (op.G / op.k).T.astype(np.float64)[ids // req.n_ic]
     err = np.abs(req.result.x.cpu().numpy()[ids] - ref.x) / gk
     assert np.sum(err.max(axis=1) > 1e-4) <= 1
+
+
+def test_full_request_tables_open_new_generations():
+    # Request tables of three entries: a stream of twelve requests of one
+    # network class runs through several step servers; drained ones are
+    # destroyed, and every result still equals its one-shot solve.
+    rng = np.random.default_rng(11)
+    topo = inputs.erdos_renyi(10, 25, 1002)
+    reqs = [Request(i, topo, 900 + i, int(rng.integers(20, 200)), 5, arrival=0.002 * i) for i in range(12)]
+    ex = GpuExecutor(batch_steps=32, max_requests=3)
+    sched = Scheduler(ex, hbm_budget=1 << 30)
+    peak = 0
+    orig = ex.start
+
+    def start(req):
+        nonlocal peak
+        orig(req)
+        peak = max(peak, ex.generations())
+
+    ex.start = start
+    done = sched.run(reqs, max_seconds=120)
+    assert len(done) == 12
+    say("generations alive at most:", peak, "at the end:", ex.generations())
+    assert peak >= 2                       # twelve requests cannot fit one table of three
+    assert ex.generations() <= 2           # drained generations were destroyed
+    for req in done:
+        T = req.handle["T"]
+        prm = rp.sample_params(T, req.seed, req.n_sets, req.n_ic).to_device()
+        ref = _direct(T, prm, req.handle["class"][0])
+        assert torch.equal(req.result.x, ref.x), req.rid
