@@ -161,6 +161,23 @@ def test_lane_choices():
     assert not ts.lanes_supported(3)
 
 
+def test_largest_supported_networks_and_one_past_them():
+    # FP32: 64 lanes x 8 gene slots bound N at 512; 1,024 edges fit 16 edge
+    # slots per lane.  FP64 kernels stop at 4 gene slots with 8 edge slots.
+    big = rp.Topology.from_inputs(inputs.erdos_renyi(512, 1024, 7))
+    assert big.auto_lanes(rp.FP32) == 64 and big.shape(64, rp.FP32) == (16, 8)
+    assert big.auto_lanes(rp.FP64) == 0
+    big64 = rp.Topology.from_inputs(inputs.erdos_renyi(256, 400, 7))
+    assert big64.auto_lanes(rp.FP64) == 64 and big64.shape(64, rp.FP64) == (8, 4)
+    # One gene more than 64 x 8: rejected before anything is enqueued.
+    past = rp.Topology.from_inputs(inputs.erdos_renyi(513, 1000, 7))
+    assert past.auto_lanes(rp.FP32) == 0
+    with pytest.raises(rp.RacError) as e:
+        rp.steady_states(past, _fake_params(513, 1000, 4, 2), rp.Opts(), out=_fake_result(),
+                         stream=type("S", (), {"cuda_stream": 0})())
+    assert e.value.code == rp.EUNSUPPORTED
+
+
 def test_factor_form_switch_point():
     # FP32 kernels of up to 16 edge slots use the base-free Hill factor; wider
     # FP32 and all FP64 kernels the symmetric one.

@@ -200,6 +200,15 @@ def test_largest_network():
     case.check(opts_for(rp.FP32), label="N100")
 
 
+@pytest.mark.parametrize("prec,N,E", [(rp.FP32, 512, 1024), (rp.FP64, 256, 400)])
+def test_largest_compiled_shapes(prec, N, E):
+    # The largest networks the compiled kernels take: 64 lanes per trajectory
+    # with every gene slot of the (16, 8) FP32 or (8, 4) FP64 shape in use.
+    case = Case(inputs.erdos_renyi(N, E, 7), 31, 4, 2)
+    assert case.T.auto_lanes(prec) == 64
+    case.check(opts_for(prec), label=f"N{N}")
+
+
 def test_unregulated_gene_closed_form():
     case = Case(inputs.unregulated(1), 4, 300, 2)
     opts = opts_for(rp.FP32)
