@@ -149,6 +149,41 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def parity_report(topo, seed, n_sets, n_ic, ids, x_rows, opts_kw, t_out=None):
+    """The FP64 oracle on trajectories `ids` of the workload against the GPU's
+    results for them (x_rows, host, same order): the per-component error
+    normalised by G/k (the parity metric, tolerance 1e-4) and the plain
+    relative error.  A report for the bench line; the parity tests are the
+    pass/fail checks (they also adjudicate basin flips near separatrices and
+    stops on slow manifolds)."""
+    import oracle
+    net = oracle.canonicalize(topo.n_genes, topo.src, topo.dst, topo.sign)
+    op = oracle.sample(net, seed, n_sets, n_ic)
+    o = oracle.Opts(**opts_kw)
+    threads = min(os.cpu_count() or 1, 16)
+    if t_out is None:
+        ref = oracle.steady_states(net, op, o, traj_ids=ids, n_threads=threads)
+    else:
+        ref = oracle.time_series(net, op, t_out, o, traj_ids=ids, n_threads=threads)
+    gk = (op.G.astype(np.float64) / op.k.astype(np.float64)).T[ids // n_ic]
+    if t_out is not None:
+        gk = gk[:, None, :]
+    x = np.asarray(x_rows, dtype=np.float64)
+    d = np.abs(x - ref.x)
+    err = d / gk
+    rel = d / np.maximum(np.abs(ref.x), 1e-12)
+    per_traj = err.reshape(len(ids), -1).max(axis=1)
+    rec = {"n": int(len(ids)), "max_norm_err": float(err.max()),
+           "p99_norm_err": float(np.percentile(err, 99)),
+           "rel_p50": float(np.percentile(rel, 50)), "rel_p99": float(np.percentile(rel, 99)),
+           "trajectories_over_1e-4": int((per_traj > 1e-4).sum()),
+           "what": "GPU FP32 vs the FP64 oracle on a seeded sample; error = |x_gpu - x_ref| / (G/k) "
+                   "per component"}
+    if t_out is not None:
+        rec["max_norm_err_every_10th_time"] = [float(v) for v in err.max(axis=(0, 2))[::10]]
+    return rec
+
+
 def cpu_oracle_multi(nets, n_pilot, target_s=12.0):
     """cpu_oracle over several networks: nets = [(topo, seed, n_sets, n_ic)];
     the sample draws trajectories across networks in proportion to their
@@ -226,6 +261,7 @@ def bench_er10(args, torch, rp, flops, inputs):
     wall, lat = timed(step, args.steps, stream, torch)
     nacc = out.n_acc.cpu().numpy().astype(np.int64)
     nrej = out.n_rej.cpu().numpy().astype(np.int64)
+    x_er10 = out.x.cpu().numpy()
     value = solved(rp, out.status) * args.steps / wall
     achieved = flops.credited(T.n_genes, hp.n, args.n_ic, nacc + nrej) / (lat.mean() * 1e-3)
     nbytes = flops.algorithmic_bytes(T.n_genes, T.n_edges, args.n_sets, args.n_ic, 4)
@@ -321,6 +357,9 @@ def bench_er10(args, torch, rp, flops, inputs):
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_oracle(topo, 2002, args.n_sets, args.n_ic, args.cpu_sample or 20000,
                                           gpu_steps=nacc + nrej)
+        ids = np.sort(np.random.default_rng(1).choice(n_traj, min(n_traj, 10000), replace=False))
+        rec["parity"] = parity_report(topo, 2002, args.n_sets, args.n_ic, ids, x_er10[ids],
+                                      {"ss_rtol": 1e-5})
     return rec
 
 
@@ -338,6 +377,7 @@ def bench_ts(args, torch, rp, flops, inputs):
         wall, lat = timed(fn, args.steps, stream, torch)
         res[name] = {"solves_per_s": solved(rp, out.status) * args.steps / wall,
                      "kernel_ms": float(lat.mean())}
+        x_last = out.x.cpu().numpy()
     rec = base_record(args)
     rec.update({"value": res["fp32"]["solves_per_s"], "unit": "solves/s",
                 "ms_per_step": res["fp32"]["kernel_ms"],
@@ -346,6 +386,9 @@ def bench_ts(args, torch, rp, flops, inputs):
                 "forms": res})
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_oracle(topo, 2001, 1000, 10, 2000, {"ss_rtol": 0.0})
+        # The whole ensemble, FP32 form (the last one run) against the oracle
+        # with the FP32 steady criterion.
+        rec["parity"] = parity_report(topo, 2001, 1000, 10, np.arange(10000), x_last, {"ss_rtol": 1e-5})
     return rec
 
 
@@ -394,6 +437,18 @@ def bench_uneven64(args, torch, rp, flops, inputs):
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_oracle_multi(
             [(t, 3000 + i, P, 10) for i, (t, P) in enumerate(zip(topos, Ps))], 4000)
+        # 200 seeded trajectories of every network.
+        reps = []
+        prng = np.random.default_rng(2)
+        for i, (t, P, o) in enumerate(zip(topos, Ps, outs)):
+            ids = np.sort(prng.choice(P * 10, 200, replace=False))
+            reps.append(parity_report(t, 3000 + i, P, 10, ids, o.x.cpu().numpy()[ids], {"ss_rtol": 1e-5}))
+        rec["parity"] = {"n": sum(r["n"] for r in reps),
+                         "max_norm_err": max(r["max_norm_err"] for r in reps),
+                         "trajectories_over_1e-4": sum(r["trajectories_over_1e-4"] for r in reps),
+                         "networks": len(reps),
+                         "what": "GPU FP32 vs the FP64 oracle, 200 seeded trajectories per network; "
+                                 "error = |x_gpu - x_ref| / (G/k) per component"}
     return rec
 
 
@@ -413,6 +468,9 @@ def bench_core22ts(args, torch, rp, flops, inputs):
     steps = out.n_acc.cpu().numpy().astype(np.int64) + out.n_rej.cpu().numpy()
     fl = flops.credited(T.n_genes, hp.n, n_ic, steps)
     v32 = solved(rp, out.status) * args.steps / wall
+    # 1 % seeded sample of the series kept on the host for the parity report.
+    par_ids = np.sort(np.random.default_rng(3).choice(P * n_ic, (P * n_ic) // 100, replace=False))
+    x_par = out.x[torch.from_numpy(par_ids).to(out.x.device)].cpu().numpy()
     del out
     o64 = rp.Opts(precision=rp.FP64)
     out64 = rp.alloc_result(P * n_ic, T.n_genes, rp.FP64, n_t=101)
@@ -438,6 +496,7 @@ def bench_core22ts(args, torch, rp, flops, inputs):
                 "speedup_fp32_vs_fp64": v32 / v64})
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_oracle(topo, 2004, P, n_ic, 1000, {"ss_rtol": 1e-5}, t_out=tk)
+        rec["parity"] = parity_report(topo, 2004, P, n_ic, par_ids, x_par, {"ss_rtol": 1e-5}, t_out=tk)
     return rec
 
 
