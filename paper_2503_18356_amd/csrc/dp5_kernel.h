@@ -368,8 +368,8 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
 
     // Write the end-of-trajectory record and free the group.
     auto finish = [&](int status) {
-        const NetDesc* dp = a.nets ? a.nets + rec->net : nullptr;
-#define RAC_DF(field) (dp ? dp->field : a.net0.field)
+        const NetDesc* dp = a.nets + rec->net;
+#define RAC_DF(field) (dp->field)
         const int N = RAC_DF(n_genes);
         const int64_t local = traj - RAC_DF(traj_begin);
         R* const xo = (R*)RAC_DF(x_out) + local * (int64_t)(TS ? a.n_t : 1) * N;
@@ -415,23 +415,20 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
     // its network, load and derive its parameters, set x0.
     auto load_traj = [&](int64_t idx) {
             // Which network: binary search over first queue indices.
-            int net = 0;
-            if (a.nets) {
-                int lo = 0, hi = (BOUNDED ? __hip_atomic_load(&a.ctl->n_nets, __ATOMIC_RELAXED,
-                                                               __HIP_MEMORY_SCOPE_AGENT)
-                                          : a.n_nets) - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (a.nets[mid].traj_begin <= idx) lo = mid; else hi = mid - 1;
-                }
-                net = lo;
+            int lo = 0, hi = (BOUNDED ? __hip_atomic_load(&a.ctl->n_nets, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT)
+                                      : a.n_nets) - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (a.nets[mid].traj_begin <= idx) lo = mid; else hi = mid - 1;
             }
+            const int net = lo;
             // Loads go one slot at a time (the memory clobbers stop
             // the scheduler from hoisting them all), which keeps
             // this rarely taken path from setting the kernel's
             // register peak next to the live trajectory state.
-            const NetDesc* dp = a.nets ? a.nets + net : nullptr;
-#define RAC_DF(field) (dp ? dp->field : a.net0.field)
+            const NetDesc* dp = a.nets + net;
+#define RAC_DF(field) (dp->field)
             traj = idx;
             const int64_t local = idx - RAC_DF(traj_begin);
             const int n_ic = RAC_DF(n_ic);
@@ -680,10 +677,10 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
             const int n_genes = rec->n_genes;
             const float d0 = sqrtf(group_sumf(s0) / n_genes), d1 = sqrtf(group_sumf(s1) / n_genes);
             if (TS && fresh) {
-                const NetDesc* dp = a.nets ? a.nets + rec->net : nullptr;
-                const int N = dp ? dp->n_genes : a.net0.n_genes;
-                const int64_t local = traj - (dp ? dp->traj_begin : a.net0.traj_begin);
-                R* xo = (R*)(dp ? dp->x_out : a.net0.x_out) + local * (int64_t)a.n_t * N;
+                const NetDesc* dp = a.nets + rec->net;
+                const int N = dp->n_genes;
+                const int64_t local = traj - (dp->traj_begin);
+                R* xo = (R*)(dp->x_out) + local * (int64_t)a.n_t * N;
                 while (kout < a.n_t && a.t_out[kout] <= t) {
 #pragma unroll
                     for (int q = 0; q < GPL; ++q)
@@ -807,10 +804,10 @@ __global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
         }
         // Dense output for every output time inside the accepted step.
         if (TS && accept && kout < a.n_t && a.t_out[kout] <= (clipped ? t_stop : t + hs)) {
-            const NetDesc* dp = a.nets ? a.nets + rec->net : nullptr;
-            const int N = dp ? dp->n_genes : a.net0.n_genes;
-            const int64_t local = traj - (dp ? dp->traj_begin : a.net0.traj_begin);
-            R* xo = (R*)(dp ? dp->x_out : a.net0.x_out) + local * (int64_t)a.n_t * N;
+            const NetDesc* dp = a.nets + rec->net;
+            const int N = dp->n_genes;
+            const int64_t local = traj - (dp->traj_begin);
+            R* xo = (R*)(dp->x_out) + local * (int64_t)a.n_t * N;
             const double t_new = clipped ? t_stop : t + hs;
             while (kout < a.n_t && a.t_out[kout] <= t_new) {
                 const R th = (R)((a.t_out[kout] - t) / hs);

@@ -66,8 +66,10 @@ struct ServeCtl {
 };
 
 struct LaunchArgs {
-    const NetDesc* nets;  // device array when n_nets > 1, else nullptr
-    NetDesc net0;         // the network when nets == nullptr
+    // Device array of the launch's networks, also for a single one: the
+    // kernel reads descriptors from memory on its rare paths (trajectory
+    // start and end) instead of holding them in scalar registers.
+    const NetDesc* nets;
     int32_t n_nets;
     int64_t total;        // trajectories over all networks
     unsigned long long* counter;

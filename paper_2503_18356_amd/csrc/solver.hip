@@ -126,8 +126,13 @@ void free_device_plans(rac_topology* t) {
 namespace {
 
 // Zero the queue counter with a kernel (no memset node in captured graphs).
-__global__ void zero_counter(unsigned long long* p) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0ull;
+// Zero the queue counter and, for a single network, store its descriptor
+// (no host copy for the common one-network launch).
+__global__ void setup_launch(unsigned long long* counter, NetDesc* table, NetDesc one) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *counter = 0ull;
+        if (table) *table = one;
+    }
 }
 
 rac_status check_opts(const rac_solver_opts* o, const char* who) {
@@ -290,27 +295,24 @@ rac_status launch_group(const std::vector<Job>& jobs, int lpt, const rac_solver_
 
     // Per-call device block: queue counter, network table, output times.
     const size_t off_nets = 256;
-    const size_t off_t = off_nets + (descs.size() > 1 ? descs.size() * sizeof(NetDesc) : 0);
+    const size_t off_t = off_nets + (descs.size() * sizeof(NetDesc) + 255) / 256 * 256;
     const size_t bytes = off_t + (ts ? sizeof(double) * n_t : 0);
     void* blk = nullptr;
     RAC_HIP(hipMallocAsync(&blk, bytes, stream), "hipMallocAsync");
     char* b = (char*)blk;
     a.counter = (unsigned long long*)b;
-    if (descs.size() > 1) {
-        a.nets = (const NetDesc*)(b + off_nets);
+    a.nets = (const NetDesc*)(b + off_nets);
+    if (descs.size() > 1)
         RAC_HIP(hipMemcpyAsync(b + off_nets, descs.data(), descs.size() * sizeof(NetDesc),
                                hipMemcpyHostToDevice, stream), "hipMemcpyAsync(nets)");
-    } else {
-        a.nets = nullptr;
-        a.net0 = descs[0];
-    }
     if (ts) {
         a.t_out = (const double*)(b + off_t);
         RAC_HIP(hipMemcpyAsync(b + off_t, host_t_out, sizeof(double) * n_t, hipMemcpyHostToDevice, stream),
                 "hipMemcpyAsync(t_out)");
     }
-    hipLaunchKernelGGL(zero_counter, dim3(1), dim3(64), 0, stream, a.counter);
-    RAC_HIP(hipGetLastError(), "zero_counter launch");
+    hipLaunchKernelGGL(setup_launch, dim3(1), dim3(64), 0, stream, a.counter,
+                       descs.size() == 1 ? (NetDesc*)(b + off_nets) : nullptr, descs[0]);
+    RAC_HIP(hipGetLastError(), "setup_launch");
     void* args[] = {&a};
     RAC_HIP(hipLaunchKernel(ke->fn, dim3(grid), dim3(kBlock), args, 0, stream), "dp5 kernel launch");
     RAC_HIP(hipFreeAsync(blk, stream), "hipFreeAsync");
