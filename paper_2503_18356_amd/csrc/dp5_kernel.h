@@ -231,8 +231,19 @@ struct alignas(2 * sizeof(R)) RatePair {
     R G, k;
 };
 
+// Waves per SIMD the compiler is asked to fit (1: no request).  The FP32
+// steady-state (11, 3) shape needs 129 VGPRs unasked, one over the four-wave
+// budget, and fits 128 without spilling when asked (9.6 % faster on a 22-gene
+// network).  Other shapes would spill to reach the next occupancy, and
+// reloads inside the step loop cost more than the extra wave gains.
+template <typename R, int EPL, int GPL, bool TS, bool BOUNDED>
+constexpr int requested_waves() {
+    return (sizeof(R) == 4 && !TS && !BOUNDED && EPL == 11 && GPL == 3) ? 4 : 1;
+}
+
 template <typename R, int EPL, int GPL, bool TS, bool BOUNDED = false, int M = kDP5>
-__global__ __launch_bounds__(kBlock) void dp5_kernel(LaunchArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(requested_waves<R, EPL, GPL, TS, BOUNDED>(), 8)))
+void dp5_kernel(LaunchArgs a) {
     static_assert(!(TS && BOUNDED), "serving step batches run in steady-state mode");
     using O = Ops<R>;
     using NT = typename O::NType;
