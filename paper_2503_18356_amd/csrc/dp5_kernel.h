@@ -231,14 +231,21 @@ struct alignas(2 * sizeof(R)) RatePair {
     R G, k;
 };
 
-// Waves per SIMD the compiler is asked to fit (1: no request).  The FP32
-// steady-state (11, 3) shape needs 129 VGPRs unasked, one over the four-wave
-// budget, and fits 128 without spilling when asked (9.6 % faster on a 22-gene
-// network).  Other shapes would spill to reach the next occupancy, and
-// reloads inside the step loop cost more than the extra wave gains.
+// Waves per SIMD the compiler is asked to fit (1: no request), for the FP32
+// shapes that sit a few VGPRs above an occupancy step and fit below it
+// without spilling when asked: steady-state (11, 3) 129 -> 128 (4 waves,
+// 9.6 % faster on a 22-gene network); serving step batches (4, 2) 97 -> 95
+// (5 waves), (12, 2) 130 -> 128 (4), (13, 5) 171 -> 168 and (16, 4) 170 -> 168
+// (3).  Other shapes would spill to reach the next occupancy, and reloads
+// inside the step loop cost more than the extra wave gains.
 template <typename R, int EPL, int GPL, bool TS, bool BOUNDED>
 constexpr int requested_waves() {
-    return (sizeof(R) == 4 && !TS && !BOUNDED && EPL == 11 && GPL == 3) ? 4 : 1;
+    if (sizeof(R) != 4 || TS) return 1;
+    if (!BOUNDED) return (EPL == 11 && GPL == 3) ? 4 : 1;
+    if (EPL == 4 && GPL == 2) return 5;
+    if (EPL == 12 && GPL == 2) return 4;
+    if ((EPL == 13 && GPL == 5) || (EPL == 16 && GPL == 4)) return 3;
+    return 1;
 }
 
 template <typename R, int EPL, int GPL, bool TS, bool BOUNDED = false, int M = kDP5>
