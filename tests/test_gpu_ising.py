@@ -18,7 +18,8 @@ def say(*a):
     print(*a, flush=True)
 
 
-def _check(topo, n_traj, mode, low, max_steps, seed, sample, order=None, check_every=0, init=None):
+def _check(topo, n_traj, mode, low, max_steps, seed, sample, order=None, check_every=0, init=None,
+           extra_ids=()):
     T = rp.Topology.from_inputs(topo)
     dev_init = None
     if init is not None:
@@ -31,6 +32,7 @@ def _check(topo, n_traj, mode, low, max_steps, seed, sample, order=None, check_e
     J = oi.coupling(topo.n_genes, topo.src, topo.dst, topo.sign)
     ids = np.arange(n_traj) if sample >= n_traj else np.sort(
         np.random.default_rng(seed).choice(n_traj, sample, replace=False))
+    ids = np.unique(np.concatenate([ids, np.asarray(extra_ids, np.int64)]))
     for t in ids:
         s0 = init[t] if init is not None else oi.random_state(seed, int(t), topo.n_genes)
         f, k, ss, _ = oi.run(J, s0, mode, low, max_steps, seed, order, check_every, traj=int(t))
@@ -72,3 +74,44 @@ def test_bad_orders_are_rejected():
         rp.ising(T, 4, rp.ISING_ASYNC, order=[0, 2])
     with pytest.raises(rp.RacError):
         rp.ising(T, 4, rp.ISING_SYNC, low=1)
+
+
+def test_sync_large_ragged_ensemble():
+    # 600,001 random states: checked at wave and block boundaries and at the
+    # last trajectory, besides a random sample.
+    n = 600_001
+    edges = [0, 1, 63, 64, 127, 128, 2047, 2048, 4095, n - 129, n - 65, n - 64, n - 2, n - 1]
+    for low in (0, -1):
+        _check(inputs.dense_core(1004), n, "sync", low, 300, 5, 40, extra_ids=edges)
+
+
+def _wide_fan_in(n_genes, seed):
+    # Random sparse edges plus genes regulated by 64, 40, 17, 9 and 5 others,
+    # self-loops, and genes without regulators.
+    rng = np.random.default_rng(seed)
+    edges = {}
+    for s_, d_ in zip(rng.integers(0, n_genes, 2 * n_genes), rng.integers(0, n_genes, 2 * n_genes)):
+        edges[(int(s_), int(d_))] = 1 if rng.random() < 0.5 else -1
+    for target, fan in ((0, min(64, n_genes)), (1, 40), (2, 17), (3, 9), (4, 5)):
+        for s_ in rng.choice(n_genes, fan, replace=False):
+            edges[(int(s_), target)] = 1 if rng.random() < 0.5 else -1
+    for g in (5, 6, 7):
+        edges[(g, g)] = 1 if g % 2 else -1
+    for g in (n_genes - 1, n_genes - 2):  # no regulators
+        edges = {k: v for k, v in edges.items() if k[1] != g}
+    src = np.array([k[0] for k in edges], np.int32)
+    dst = np.array([k[1] for k in edges], np.int32)
+    sign = np.array(list(edges.values()), np.int8)
+    return inputs.Topology(n_genes, src, dst, sign, f"fanin{n_genes}")
+
+
+@pytest.mark.parametrize("n_genes", [64, 65])
+def test_sync_wide_fan_in(n_genes):
+    # Regulator counts up to 64 (the popcounts of a full state word), self-
+    # loops, genes without regulators; 64 genes fill one state word, 65 need
+    # two.  Given initial states, both off values.
+    topo = _wide_fan_in(n_genes, 23)
+    rng = np.random.default_rng(n_genes)
+    init = rng.random((3000, n_genes)) < 0.5
+    for low in (0, -1):
+        _check(topo, 3000, "sync", low, 500, 9, 60, init=init, extra_ids=[0, 2999])
