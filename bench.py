@@ -585,8 +585,8 @@ def main():
                          "counters scale the kernel's HBM traffic figures")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(trajectories are independent; the sharding design is in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (trajectories are "
+              "independent, so several GPUs would each take a share of the ensemble)", file=sys.stderr)
         sys.exit(2)
     if args.serve_requests is None:
         args.serve_requests = 2000 if args.workload == "serve" else 300
