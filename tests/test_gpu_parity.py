@@ -262,3 +262,29 @@ def test_options_no_division_and_absolute_ic(prec):
     case.op.ic[:] = case.op.ic * 50.0
     case.dp.ic.mul_(50.0)
     case.check(opts_for(prec, ic_absolute=1), label="abs-ic")
+
+
+@pytest.mark.parametrize("prec", [rp.FP32, rp.FP64])
+@pytest.mark.parametrize("times", [[0.0], [37.5], [5.0, 10.0, 20.0], list(np.linspace(0.0, 1.0, 201))],
+                         ids=["t0-only", "one-late", "late-start", "dense"])
+def test_time_series_output_grids(prec, times):
+    # A single output at t0 (the initial state, no step taken), a single later
+    # output, a grid that starts after t0, and outputs spaced far closer than
+    # the steps (several per step, from the continuous extension).
+    case = Case(inputs.erdos_renyi(6, 14, 31), 41, 30, 3)
+    tk = np.asarray(times, np.float64)
+    opts = opts_for(prec)
+    say(f"[gpu] time series grid n_t={tk.size} first={tk[0]} prec={prec}")
+    out = rp.integrate(case.T, case.dp, tk, opts)
+    torch.cuda.synchronize()
+    ref = oracle.time_series(case.net, case.op, tk, case.oracle_opts(opts), n_threads=THREADS)
+    st = out.status.cpu().numpy()
+    assert np.all(st == rp.T_END), np.bincount(st)
+    assert np.allclose(out.t_final.cpu().numpy(), tk[-1])
+    x = out.x.cpu().numpy()
+    assert x.shape == (case.n_traj, tk.size, case.T.n_genes)
+    err, _ = parity.compare_series(case.op, np.arange(case.n_traj), x, ref.x, case.n_ic)
+    say("    max normalised error", float(err.max()))
+    assert err.max() <= parity.TOL, (err.argmax(), err.max())
+    if tk[0] == 0.0:
+        assert np.allclose(x[:, 0, :], ref.x[:, 0, :], rtol=1e-6)
