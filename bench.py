@@ -214,7 +214,7 @@ def cpu_oracle_multi(nets, n_pilot, target_s=12.0):
                       f"DP5(4), {threads} threads, {cw:.1f} s wall"}
 
 
-def serving_run(n_req, warm, rate, seed=5, budget=64 << 30, batch_steps=256):
+def serving_run(n_req, warm, rate, seed=5, budget=64 << 30, batch_steps=512):
     from paper_2503_18356_amd.serve import GpuExecutor, Scheduler, poisson_requests
     rng = np.random.default_rng(seed)
     reqs = poisson_requests(rng, n_req + warm, rate=rate)

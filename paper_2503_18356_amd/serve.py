@@ -168,7 +168,7 @@ class GpuExecutor:
     completed.  A class under continuous load therefore runs indefinitely
     with at most a few generations alive."""
 
-    def __init__(self, opts=None, batch_steps: int = 256, max_requests: int = 65536,
+    def __init__(self, opts=None, batch_steps: int = 512, max_requests: int = 65536,
                  device="cuda", keep_results: bool = True, merge_slack: float = 2.0,
                  n_streams: int = 4):
         import torch
