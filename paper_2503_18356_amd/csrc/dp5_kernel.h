@@ -387,10 +387,9 @@ void dp5_kernel(LaunchArgs a) {
     // Write the end-of-trajectory record and free the group.
     auto finish = [&](int status) {
         const NetDesc* dp = a.nets + rec->net;
-#define RAC_DF(field) (dp->field)
-        const int N = RAC_DF(n_genes);
-        const int64_t local = traj - RAC_DF(traj_begin);
-        R* const xo = (R*)RAC_DF(x_out) + local * (int64_t)(TS ? a.n_t : 1) * N;
+        const int N = dp->n_genes;
+        const int64_t local = traj - dp->traj_begin;
+        R* const xo = (R*)dp->x_out + local * (int64_t)(TS ? a.n_t : 1) * N;
         if (!TS) {
 #pragma unroll
             for (int q = 0; q < GPL; ++q)
@@ -403,18 +402,17 @@ void dp5_kernel(LaunchArgs a) {
                     if (is_real(q)) xo[(int64_t)k * N + gene_of(q)] = x[q];
         }
         if (r == 0) {
-            double* tf = RAC_DF(t_final);
-            int8_t* sp = RAC_DF(status);
-            int32_t* na = RAC_DF(n_acc);
-            int32_t* nr = RAC_DF(n_rej);
+            double* tf = dp->t_final;
+            int8_t* sp = dp->status;
+            int32_t* na = dp->n_acc;
+            int32_t* nr = dp->n_rej;
             if (tf) tf[local] = t;
             if (sp) sp[local] = (int8_t)status;
             if (na) na[local] = nacc;
             if (nr) nr[local] = nrej;
-            int32_t* dn = RAC_DF(done);
+            int32_t* dn = dp->done;
             if (dn) atomicAdd(dn, 1);
         }
-#undef RAC_DF
         traj = -1;
         fresh = false;
     };
@@ -446,22 +444,21 @@ void dp5_kernel(LaunchArgs a) {
             // this rarely taken path from setting the kernel's
             // register peak next to the live trajectory state.
             const NetDesc* dp = a.nets + net;
-#define RAC_DF(field) (dp->field)
             traj = idx;
-            const int64_t local = idx - RAC_DF(traj_begin);
-            const int n_ic = RAC_DF(n_ic);
-            int64_t p = (int64_t)((double)local * RAC_DF(inv_n_ic));
+            const int64_t local = idx - dp->traj_begin;
+            const int n_ic = dp->n_ic;
+            int64_t p = (int64_t)((double)local * dp->inv_n_ic);
             if (p * n_ic > local) --p;
             if ((p + 1) * n_ic <= local) ++p;
             const int ci = (int)(local - p * n_ic);
-            const int64_t P = RAC_DF(n_sets);
-            const int n_genes = RAC_DF(n_genes);
+            const int64_t P = dp->n_sets;
+            const int n_genes = dp->n_genes;
             *rec = GroupRec{1.0 / n_genes, n_genes, net};
-            const int stride = RAC_DF(stride);
-            const int32_t* lane_edge = RAC_DF(lane_edge) + r * stride;
-            const float* Tp = RAC_DF(T) + p;
-            const float* Lp = RAC_DF(lam) + p;
-            const uint8_t* Np = RAC_DF(n) + p;
+            const int stride = dp->stride;
+            const int32_t* lane_edge = dp->lane_edge + r * stride;
+            const float* Tp = dp->T + p;
+            const float* Lp = dp->lam + p;
+            const uint8_t* Np = dp->n + p;
             // Only the loads are conditional: padding slots take T = lam = n = 1,
             // an inhibiting sign and the sink, which the same formulas turn
             // into a factor of exactly 1 (every array element is written on
@@ -499,13 +496,12 @@ void dp5_kernel(LaunchArgs a) {
                     e_d[s] = (R)1 / sl - sl;
                 }
             }
-            const float* Gp = RAC_DF(G) + p;
-            const float* Kp = RAC_DF(k) + p;
-            const float* icp = RAC_DF(ic) + (int64_t)ci * n_genes;
-            const int32_t* row_ptr = RAC_DF(row_ptr);
-            const int32_t* gene_row = RAC_DF(gene_row);
-            const int8_t* sign = RAC_DF(sign);
-#undef RAC_DF
+            const float* Gp = dp->G + p;
+            const float* Kp = dp->k + p;
+            const float* icp = dp->ic + (int64_t)ci * n_genes;
+            const int32_t* row_ptr = dp->row_ptr;
+            const int32_t* gene_row = dp->gene_row;
+            const int8_t* sign = dp->sign;
             // As for edges: conditional loads, one unconditional write per
             // element; padding genes get G = k = 0 and the sink.
 #pragma unroll
