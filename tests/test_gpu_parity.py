@@ -288,3 +288,49 @@ def test_time_series_output_grids(prec, times):
     assert err.max() <= parity.TOL, (err.argmax(), err.max())
     if tk[0] == 0.0:
         assert np.allclose(x[:, 0, :], ref.x[:, 0, :], rtol=1e-6)
+
+
+def test_uneven_batch_full_size_sampled():
+    # The 64-network uneven batch at its benchmark sizes (P log-uniform in
+    # [2,000, 50,000] sets x 10 ICs, about 10^7 trajectories) in one call, as
+    # the benchmark launches it; 20 seeded trajectories of every network
+    # against the oracle.
+    rng = np.random.default_rng(1003)
+    topos = inputs.uneven_batch(1003, n_networks=64, n_min=5, n_max=50)
+    Ps = [inputs.log_uniform_int(rng, 2000, 50000) for _ in topos]
+    cases = [Case(t, 3000 + i, P, 10) for i, (t, P) in enumerate(zip(topos, Ps))]
+    opts = opts_for(rp.FP32)
+    say(f"[gpu] uneven batch, {sum(c.n_traj for c in cases)} trajectories")
+    outs = rp.steady_states_batch([(c.T, c.dp) for c in cases], opts)
+    torch.cuda.synchronize()
+    prng = np.random.default_rng(4)
+    worst = 0.0
+    for c, o in zip(cases, outs):
+        traj = np.sort(prng.choice(c.n_traj, 20, replace=False))
+        oo = c.oracle_opts(opts)
+        ref = oracle.steady_states(c.net, c.op, oo, traj_ids=traj, n_threads=THREADS)
+        rep = parity.compare_steady(c.net, c.op, oo, traj, o.x.cpu().numpy()[traj], ref.x, c.n_ic)
+        assert rep.ok(), (c.topo.name, rep)
+        worst = max(worst, rep.max_err)
+    say("    worst normalised error over 64 networks:", worst)
+
+
+def test_time_series_full_size_sampled():
+    # The 22-gene series at its benchmark size: 10^5 sets x 10 ICs, 101
+    # outputs on [0, 100] (8.9 GB of outputs); 200 seeded trajectories
+    # against the oracle at every output time.
+    case = Case(inputs.dense_core(1004), 2004, 100000, 10)
+    tk = np.linspace(0.0, 100.0, 101)
+    say("[gpu] 22-gene series, 10^6 trajectories x 101 times")
+    out = rp.integrate(case.T, case.dp, tk, opts_for(rp.FP32))
+    torch.cuda.synchronize()
+    traj = np.sort(np.random.default_rng(9).choice(case.n_traj, 200, replace=False))
+    xs = out.x[torch.from_numpy(traj).to(out.x.device)].cpu().numpy()
+    st = out.status.cpu().numpy()
+    assert np.all(st == rp.T_END), np.bincount(st)
+    del out
+    ref = oracle.time_series(case.net, case.op, tk, case.oracle_opts(opts_for(rp.FP32)), traj_ids=traj,
+                             n_threads=THREADS)
+    err, _ = parity.compare_series(case.op, traj, xs, ref.x, case.n_ic)
+    say("    max normalised error", float(err.max()))
+    assert err.max() <= parity.TOL, (err.argmax(), err.max())
