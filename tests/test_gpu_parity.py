@@ -101,10 +101,13 @@ def test_toggle_switch_full_ensemble(prec):
         assert rep.p99_rel < 1e-9 and rep.max_err < 1e-5
 
 
-def test_er10_one_percent_of_a_million():
-    # 10-gene / 25-edge random network, 10^4 sets x 100 ICs, oracle on 1 %.
+@pytest.mark.parametrize("prec", [rp.FP32, rp.FP64])
+def test_er10_one_percent_of_a_million(prec):
+    # 10-gene / 25-edge random network, 10^4 sets x 100 ICs, oracle on 1 %:
+    # the chosen FP32 form and the plain FP64 form (with the FP32 steady
+    # criterion, as the benchmark runs it).
     case = Case(inputs.erdos_renyi(10, 25, 1002), 2002, 10000, 100)
-    case.check(opts_for(rp.FP32), sample=10000, seed=1, label="ER10")
+    case.check(opts_for(prec, ss_rtol=1e-5), sample=10000, seed=1, label="ER10")
 
 
 @pytest.mark.parametrize("prec", [rp.FP32, rp.FP64])
