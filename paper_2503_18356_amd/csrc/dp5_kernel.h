@@ -232,24 +232,38 @@ struct alignas(2 * sizeof(R)) RatePair {
 };
 
 // Waves per SIMD the compiler is asked to fit (1: no request), for the FP32
-// shapes that sit a few VGPRs above an occupancy step and fit below it
-// without spilling when asked: steady-state (11, 3) 129 -> 128 (4 waves,
-// 9.6 % faster on a 22-gene network); serving step batches (4, 2) 97 -> 95
-// (5 waves), (12, 2) 130 -> 128 (4), (13, 5) 171 -> 168 and (16, 4) 170 -> 168
-// (3).  Other shapes would spill to reach the next occupancy, and reloads
-// inside the step loop cost more than the extra wave gains.
-template <typename R, int EPL, int GPL, bool TS, bool BOUNDED>
+// shapes that sit a few VGPRs above an occupancy step.  Asked, the compiler
+// fits them below it with no spill, or (the Tsitouras series shapes and
+// its (4, 8) steady-state shape) with three dwords of spill, whose reloads
+// cost less than the extra wave gains at two waves per SIMD: the Tsitouras
+// 22-gene series runs 24 % faster at three waves than at two, the DP5
+// 22-gene steady states 9.6 % faster at four than at three.  Shapes that
+// would spill more are not asked: their reloads inside the step loop cost
+// more than the wave (the DP5 22-gene series at four waves with 120 bytes of
+// spill runs 20 % slower).
+template <typename R, int EPL, int GPL, bool TS, bool BOUNDED, int M>
 constexpr int requested_waves() {
-    if (sizeof(R) != 4 || TS) return 1;
-    if (!BOUNDED) return (EPL == 11 && GPL == 3) ? 4 : 1;
-    if (EPL == 4 && GPL == 2) return 5;
-    if (EPL == 12 && GPL == 2) return 4;
-    if ((EPL == 13 && GPL == 5) || (EPL == 16 && GPL == 4)) return 3;
-    return 1;
+    if (sizeof(R) != 4) return 1;
+    if (BOUNDED) {  // serving step batches (DP5, steady states)
+        if (EPL == 4 && GPL == 2) return 5;
+        if (EPL == 12 && GPL == 2) return 4;
+        if ((EPL == 13 && GPL == 5) || (EPL == 16 && GPL == 4)) return 3;
+        return 1;
+    }
+    if (!TS) {
+        if (EPL == 11 && GPL == 3) return 4;
+        if (EPL == 4 && GPL == 8) return 3;
+        if (M == kTsit5 && EPL == 13 && GPL == 5) return 3;
+        return 1;
+    }
+    if (M == kDP5) return (EPL == 16 && GPL == 8) ? 2 : 1;
+    if ((EPL == 11 && GPL == 3) || (EPL == 8 && GPL == 4) || (EPL == 12 && GPL == 3) || (EPL == 16 && GPL == 2))
+        return 3;
+    return (EPL == 12 && GPL == 8) ? 2 : 1;
 }
 
 template <typename R, int EPL, int GPL, bool TS, bool BOUNDED = false, int M = kDP5>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(requested_waves<R, EPL, GPL, TS, BOUNDED>(), 8)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(requested_waves<R, EPL, GPL, TS, BOUNDED, M>(), 8)))
 void dp5_kernel(LaunchArgs a) {
     static_assert(!(TS && BOUNDED), "serving step batches run in steady-state mode");
     using O = Ops<R>;
