@@ -622,7 +622,8 @@ static double orc_initial_step(orc_stepper* s, const double* x, const double* f,
     const orc_opts* o = s->o;
     double d0 = orc_rms_scaled(x, x, N, o);
     double d1 = orc_rms_scaled(f, x, N, o);
-    double h0 = (d0 < 1e-10 || d1 < 1e-10) ? 1e-6 : 0.01 * d0 / d1;
+    /* Either norm below 1e-5: no usable scale, take 1e-6. */
+    double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
     if (h0 > hmax) h0 = hmax;
     for (int i = 0; i < N; ++i) s->y[i] = x[i] + h0 * f[i];
     orc_rhs(s->pb, s->p, o->divide_act_by_lambda, s->y, s->k[1]);

@@ -109,6 +109,8 @@ struct Ops<float> {
     __device__ static double pow_m15_sq(double err2) {
         return (double)__builtin_amdgcn_exp2f(-0.1f * __builtin_amdgcn_logf((float)err2));
     }
+    // v^(1/5) for the starting step (v > 0).
+    __device__ static float root5(float v) { return __builtin_amdgcn_exp2f(0.2f * __builtin_amdgcn_logf(v)); }
 };
 
 template <>
@@ -131,6 +133,7 @@ struct Ops<double> {
     __device__ static double abs(double v) { return __builtin_fabs(v); }
     __device__ static double sqrt(double v) { return ::sqrt(v); }
     __device__ static double pow_m15_sq(double err2) { return ::pow(err2, -0.1); }
+    __device__ static double root5(double v) { return ::pow(v, 0.2); }
 };
 
 // Wave-level ordering of LDS writes before reads by other lanes of the wave.
@@ -395,7 +398,7 @@ void dp5_kernel(LaunchArgs a) {
     auto is_steady = [&](R f, R kv, R xv) {
         return __builtin_fabs((double)f) <= c.ss_atol + c.ss_rtol * (double)kv * __builtin_fabs((double)xv);
     };
-    auto group_sumf = [&](float v) { return group_reduce(v, lpt); };
+    auto group_sumr = [&](R v) { return group_reduce(v, lpt); };
     auto group_all = [&](bool p) { return ((__ballot(p) >> gshift) & glow) == glow; };
 
     // Write the end-of-trajectory record and free the group.
@@ -680,21 +683,21 @@ void dp5_kernel(LaunchArgs a) {
         }
 
         // ---- start new trajectories: f(x0), steady test at t0, first step -
-        // (Hairer, Norsett, Wanner I, Sec. II.4 starting step; its norms are a
-        // heuristic, evaluated in FP32.)
+        // (Hairer, Norsett, Wanner I, Sec. II.4 starting step, in the state
+        // precision R.)
         if (__ballot(fresh) != 0) {
 #pragma unroll
             for (int q = 0; q < GPL; ++q) y[q] = x[q];
             rhs(y, kk[1]);
             bool fin = true, steady = true;
-            float s0 = 0, s1 = 0;
+            R s0 = 0, s1 = 0;
 #pragma unroll
             for (int q = 0; q < GPL; ++q) {
                 if (fresh) kk[0][q] = kk[1][q];
                 if (is_real(q)) {
-                    const float xv = (float)x[q], fv = (float)kk[1][q];
+                    const R xv = x[q], fv = kk[1][q];
                     fin = fin && __builtin_isfinite(xv) && __builtin_isfinite(fv);
-                    const float isc = 1.0f / ((float)c.atol + (float)c.rtol * fabsf(xv));
+                    const R isc = (R)1 / ((R)c.atol + (R)c.rtol * O::abs(xv));
                     s0 += (xv * isc) * (xv * isc);
                     s1 += (fv * isc) * (fv * isc);
                     steady = steady && is_steady(kk[1][q], rate(q).k, x[q]);
@@ -703,7 +706,7 @@ void dp5_kernel(LaunchArgs a) {
             const bool all_fin = group_all(fin);
             const bool all_steady = group_all(steady);
             const int n_genes = rec->n_genes;
-            const float d0 = sqrtf(group_sumf(s0) / n_genes), d1 = sqrtf(group_sumf(s1) / n_genes);
+            const R d0 = O::sqrt(group_sumr(s0) / (R)n_genes), d1 = O::sqrt(group_sumr(s1) / (R)n_genes);
             if (TS && fresh) {
                 const NetDesc* dp = a.nets + rec->net;
                 const int N = dp->n_genes;
@@ -716,21 +719,21 @@ void dp5_kernel(LaunchArgs a) {
                     ++kout;
                 }
             }
-            const float hmax = (float)(t_stop - c.t0);
-            float hg = (d0 < 1e-10f || d1 < 1e-10f) ? 1e-6f : 0.01f * d0 / d1;
+            const R hmax = (R)(t_stop - c.t0);
+            // Either norm below 1e-5: no usable scale, take 1e-6.
+            R hg = (d0 < (R)1e-5 || d1 < (R)1e-5) ? (R)1e-6 : (R)0.01 * d0 / d1;
             hg = hg < hmax ? hg : hmax;
 #pragma unroll
-            for (int q = 0; q < GPL; ++q) y[q] = x[q] + (R)hg * kk[0][q];
+            for (int q = 0; q < GPL; ++q) y[q] = x[q] + hg * kk[0][q];
             rhs(y, kk[2]);
-            float s2 = 0;
+            R s2 = 0;
 #pragma unroll
             for (int q = 0; q < GPL; ++q)
                 if (is_real(q)) {
-                    const float dv = (float)(kk[2][q] - kk[0][q]) /
-                                     ((float)c.atol + (float)c.rtol * fabsf((float)x[q]));
+                    const R dv = (kk[2][q] - kk[0][q]) / ((R)c.atol + (R)c.rtol * O::abs(x[q]));
                     s2 += dv * dv;
                 }
-            const float d2 = sqrtf(group_sumf(s2) / n_genes) / hg;
+            const R d2 = O::sqrt(group_sumr(s2) / (R)n_genes) / hg;
             if (fresh) {
                 if (!all_fin) {
                     finish(RAC_NONFINITE);
@@ -743,10 +746,10 @@ void dp5_kernel(LaunchArgs a) {
                     if (c.h0 > 0) {
                         h = c.h0 < hm ? c.h0 : hm;
                     } else {
-                        const float der = d1 > d2 ? d1 : d2;
-                        const float h1 = der <= 1e-15f ? fmaxf(1e-6f, hg * 1e-3f)
-                                                       : __builtin_amdgcn_exp2f(0.2f * __builtin_amdgcn_logf(0.01f / der));
-                        const double hh = (double)fminf(100.0f * hg, h1);
+                        const R der = d1 > d2 ? d1 : d2;
+                        const R h1 = der <= (R)1e-15 ? (hg * (R)1e-3 > (R)1e-6 ? hg * (R)1e-3 : (R)1e-6)
+                                                     : O::root5((R)0.01 / der);
+                        const double hh = (double)((R)100 * hg < h1 ? (R)100 * hg : h1);
                         h = hh <= hm ? hh : hm;
                     }
                     fresh = false;

@@ -3,7 +3,9 @@
 Each mutation edits one spot of ``oracle/oracle.c`` (a tableau entry, the
 division of activating terms by lambda, an edge endpoint, a sign, the
 inverted sampling of inhibitory lambda, ...), compiles the copy on the CPU,
-and runs the pins of ``test_oracle_pins`` against it: at least one must fail.
+and runs the pins of ``test_oracle_pins`` (and the step-control pins of
+``test_oracle_scipy``, the sampler and Tsit5 pins) against it: at least one
+must fail.
 """
 import contextlib
 import os
@@ -14,6 +16,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_pins as pins
+from tests import test_oracle_scipy as scipy_pins
 from tests import test_oracle_sampler as sampler
 from tests import test_oracle_tsit5 as tsit5
 
@@ -68,6 +71,28 @@ MUTATIONS = [
      [sampler.test_sobol_sampler_is_stratified_and_shifted_by_seed]),
     ("lhs jitter dropped", "return ((double)cell + jitter) / (double)lhs_n;",
      "return ((double)cell) / (double)lhs_n;", [sampler.test_lhs_sampler_one_point_per_stratum]),
+    ("controller safety factor", "double fac = err > 0 ? 0.9 * pow(err, -1.0 / 5.0) : 10.0;",
+     "double fac = err > 0 ? 0.8 * pow(err, -1.0 / 5.0) : 10.0;",
+     [lambda: scipy_pins.test_oracle_steps_like_scipy_rk45("er3", 1e-5)]),
+    ("controller exponent", "double fac = err > 0 ? 0.9 * pow(err, -1.0 / 5.0) : 10.0;",
+     "double fac = err > 0 ? 0.9 * pow(err, -1.0 / 4.0) : 10.0;",
+     [lambda: scipy_pins.test_oracle_steps_like_scipy_rk45("er3", 1e-5)]),
+    ("rejection factor", "double fac = isfinite(err) ? 0.9 * pow(err, -1.0 / 5.0) : 0.2;",
+     "double fac = isfinite(err) ? 0.5 * pow(err, -1.0 / 5.0) : 0.2;",
+     [lambda: scipy_pins.test_oracle_steps_like_scipy_rk45("toggle", 0.0)]),
+    ("growth not limited after a rejection", "double facmax = last_rejected ? 1.0 : 10.0;",
+     "double facmax = 10.0;", [lambda: scipy_pins.test_oracle_steps_like_scipy_rk45("toggle", 0.0)]),
+    ("growth limit 5", "double facmax = last_rejected ? 1.0 : 10.0;",
+     "double facmax = last_rejected ? 1.0 : 5.0;",
+     [lambda: scipy_pins.test_oracle_steps_like_scipy_rk45("er3", 1e-5)]),
+    ("starting-step threshold", "(d0 < 1e-5 || d1 < 1e-5)", "(d0 < 1e-10 || d1 < 1e-10)",
+     [scipy_pins.test_oracle_starting_step_with_tiny_state]),
+    ("starting-step exponent", "pow(0.01 / der, 1.0 / 5.0)", "pow(0.01 / der, 1.0 / 4.0)",
+     [lambda: scipy_pins.test_oracle_steps_like_scipy_rk45("cascade", 0.0)]),
+    ("steady test drops k_i", "s->o->ss_rtol * (double)s->pb->k[i * P + s->p] * fabs(x[i])",
+     "s->o->ss_rtol * fabs(x[i])", [lambda: scipy_pins.test_scaled_steady_stop_closed_form((0.2,))]),
+    ("steady test drops the relative term", "s->o->ss_rtol * (double)s->pb->k[i * P + s->p] * fabs(x[i])",
+     "0.0 * fabs(x[i])", [lambda: scipy_pins.test_scaled_steady_stop_closed_form((0.15, 0.6, 0.35))]),
     ("half-functional activation not over lambda", "if (e < n_act && r->hf_act_over_lambda) h = h / lam;",
      "", [lambda: sampler.test_half_functional_median_matches_independent_monte_carlo(1, 0)]),
 ]
