@@ -39,5 +39,6 @@ def test_autotune_choose_cache_and_parity(tmp_path):
     op = oracle.sample(net, 9, 100, 5)
     oo = oracle.Opts(ss_rtol=1e-5)
     ref = oracle.steady_states(net, op, oo, n_threads=8)
-    rep = parity.compare_steady(net, op, oo, np.arange(500), out.x.cpu().numpy(), ref.x, 5)
+    rep = parity.compare_steady(net, op, oo, np.arange(500), out.x.cpu().numpy(), ref.x, 5,
+                                out.status.cpu().numpy(), ref.status)
     assert rep.ok(), rep

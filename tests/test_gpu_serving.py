@@ -235,7 +235,8 @@ def test_both_factor_forms_agree_with_the_oracle():
     ids = np.arange(0, n_sets * n_ic, 7)
     ref = oracle.steady_states(net, op, oo, traj_ids=ids, n_threads=8)
     for name, res in (("unit", own), ("symmetric", other)):
-        rep = parity.compare_steady(net, op, oo, ids, res.x.cpu().numpy()[ids], ref.x, n_ic)
+        rep = parity.compare_steady(net, op, oo, ids, res.x.cpu().numpy()[ids], ref.x, n_ic,
+                                    res.status.cpu().numpy()[ids], ref.status)
         say(name, rep)
         assert rep.ok(), (name, str(rep))
 
