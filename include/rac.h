@@ -62,6 +62,16 @@ typedef enum {
     RAC_NONFINITE = 4       /* initial state or its derivative not finite */
 } rac_traj_status;
 
+/* The paper's steady-state flag of a status (Sec. 2.1.3 and 3.1 report a flag
+ * that is one when no steady state was reached): 0 for RAC_CONVERGED, 1 for
+ * every other status. */
+int32_t rac_not_steady_flag(int32_t status);
+
+/* The same flag for n trajectories on the device: dev_flag[i] (u8) =
+ * rac_not_steady_flag(dev_status[i]).  Stream-ordered and asynchronous;
+ * EINVAL for n < 0 or a NULL array with n > 0. */
+rac_status rac_steady_flags(const int8_t* dev_status, int64_t n, uint8_t* dev_flag, void* hip_stream);
+
 typedef enum { RAC_FP32 = 0, RAC_FP64 = 1 } rac_precision;
 
 /* Embedded Runge-Kutta 5(4) pair of the integrator.  RAC_DP5: Dormand-Prince
@@ -125,6 +135,12 @@ typedef struct {
                                      that estimate, as in Eq. 1 */
     int64_t lhs_total;            /* sets in the Latin hypercube; 0 = set_begin +
                                      n_sets (a design over exactly this call) */
+    int32_t n_continuous;         /* 0 (default): integer Hill coefficients,
+                                     uniform over n_min..n_max, written to n
+                                     (and to nf as floats when nf is given);
+                                     1: real Hill coefficients, uniform on
+                                     [n_min, n_max] (Table 1 gives the range
+                                     without a type), written to nf only */
 } rac_ranges;
 
 /* Unit-cube generators (Sec. 2.1.2).  Parameter set p is point p of the
@@ -169,9 +185,12 @@ void rac_default_ranges(rac_ranges* r);
 /* Caller-owned parameter arrays, set index fastest (SoA), stride n_sets:
  *   G[i * n_sets + p], k[i * n_sets + p]            for genes i < N,
  *   T[e * n_sets + p], lam[e * n_sets + p], n[...]  for canonical edges e < E.
- * lam is the fold change of Table 1 (activation >= 1, inhibition <= 1).  The
- * same struct describes host arrays (rac_sample_params) and device arrays
- * (integration calls). */
+ * lam is the fold change of Table 1 (activation >= 1, inhibition <= 1).  n is
+ * the integer Hill coefficient (u8); nf, when not NULL, holds real Hill
+ * coefficients (f32, > 0, same layout) and is used instead of n, which may
+ * then be NULL (Eq. 2 with a non-integer exponent).  The same struct
+ * describes host arrays (rac_sample_params) and device arrays (integration
+ * calls). */
 typedef struct {
     float* G;
     float* k;
@@ -179,6 +198,7 @@ typedef struct {
     float* lam;
     uint8_t* n;
     int64_t n_sets;
+    float* nf;
 } rac_params_view;
 
 /* Deterministic, index-addressable sampling on the host: set p depends only

@@ -41,7 +41,8 @@ class _Ranges(C.Structure):
                 ("n_min", C.c_int32), ("n_max", C.c_int32), ("t_lo", C.c_double),
                 ("t_hi", C.c_double), ("t_median", C.c_double), ("method", C.c_int32),
                 ("threshold_rule", C.c_int32), ("hf_samples", C.c_int32),
-                ("hf_act_over_lambda", C.c_int32), ("lhs_total", C.c_int64)]
+                ("hf_act_over_lambda", C.c_int32), ("lhs_total", C.c_int64),
+                ("n_continuous", C.c_int32)]
 
 
 class _Opts(C.Structure):
@@ -56,7 +57,8 @@ class _Problem(C.Structure):
     _fields_ = [("n_genes", C.c_int32), ("n_edges", C.c_int32),
                 ("src", C.c_void_p), ("dst", C.c_void_p), ("sign", C.c_void_p),
                 ("G", C.c_void_p), ("k", C.c_void_p), ("T", C.c_void_p), ("lam", C.c_void_p),
-                ("n", C.c_void_p), ("n_sets", C.c_int64), ("ic", C.c_void_p), ("n_ic", C.c_int32)]
+                ("n", C.c_void_p), ("n_sets", C.c_int64), ("ic", C.c_void_p), ("n_ic", C.c_int32),
+                ("nf", C.c_void_p)]
 
 
 _lib = None
@@ -73,7 +75,7 @@ def load(path: str):
     L.orc_gk_median.argtypes = [C.POINTER(_Ranges)]
     L.orc_gk_median.restype = C.c_double
     L.orc_sample.argtypes = [C.c_int, C.c_int, vp, vp, vp, C.POINTER(_Ranges), u64, i64, i64, i32,
-                             vp, vp, vp, vp, vp, vp]
+                             vp, vp, vp, vp, vp, vp, vp]
     L.orc_sample.restype = C.c_int
     L.orc_hf_median.argtypes = [C.POINTER(_Ranges), i32, i32]
     L.orc_hf_median.restype = C.c_double
@@ -167,6 +169,7 @@ class Ranges:
     hf_samples: int = 65536
     hf_act_over_lambda: int = 1
     lhs_total: int = 0
+    n_continuous: int = 0     # 1: real Hill coefficients on [n_min, n_max] (in Params.nf)
 
     def c(self) -> _Ranges:
         return _Ranges(*[getattr(self, f[0]) for f in _Ranges._fields_])
@@ -185,6 +188,7 @@ class Params:
     lam: np.ndarray  # [E][P] f32
     n: np.ndarray    # [E][P] u8
     ic: np.ndarray   # [n_ic][N] f32
+    nf: np.ndarray | None = None  # [E][P] f32 real Hill coefficients, used instead of n
 
     @property
     def n_sets(self) -> int:
@@ -197,13 +201,16 @@ def sample(net: Network, seed: int, n_sets: int, n_ic: int, set_begin: int = 0,
     G = np.zeros((N, P), np.float32); k = np.zeros((N, P), np.float32)
     T = np.zeros((E, P), np.float32); lam = np.zeros((E, P), np.float32)
     n = np.zeros((E, P), np.uint8); ic = np.zeros((n_ic, N), np.float32)
-    rr = (ranges or Ranges()).c()
+    rg = ranges or Ranges()
+    nf = np.zeros((E, P), np.float32) if rg.n_continuous else None
+    rr = rg.c()
     rc = lib().orc_sample(N, E, _ptr(net.src), _ptr(net.dst), _ptr(net.sign), C.byref(rr),
                           C.c_uint64(seed & (2**64 - 1)),
-                          set_begin, P, n_ic, _ptr(G), _ptr(k), _ptr(T), _ptr(lam), _ptr(n), _ptr(ic))
+                          set_begin, P, n_ic, _ptr(G), _ptr(k), _ptr(T), _ptr(lam), _ptr(n), _ptr(ic),
+                          _ptr(nf))
     if rc != 0:
         raise ValueError("orc_sample failed")
-    return Params(G, k, T, lam, n, ic)
+    return Params(G, k, T, lam, n, ic, nf)
 
 
 DP5, TSIT5 = 0, 1
@@ -267,8 +274,10 @@ class _Keep:
         s, d, g, G, k, T, lam, n, ic = self.arrs
         assert G.dtype == np.float32 and T.dtype == np.float32 and n.dtype == np.uint8
         assert ic.dtype == np.float32
+        nf = None if prm.nf is None else np.ascontiguousarray(prm.nf, dtype=np.float32)
+        self.arrs.append(nf)
         self.pb = _Problem(net.n_genes, net.n_edges, _ptr(s), _ptr(d), _ptr(g), _ptr(G), _ptr(k),
-                           _ptr(T), _ptr(lam), _ptr(n), prm.n_sets, _ptr(ic), ic.shape[0])
+                           _ptr(T), _ptr(lam), _ptr(n), prm.n_sets, _ptr(ic), ic.shape[0], _ptr(nf))
 
 
 @dataclass

@@ -101,6 +101,7 @@ void orc_default_ranges(orc_ranges* r) {
     r->hf_samples = 65536;
     r->hf_act_over_lambda = 1;
     r->lhs_total = 0;
+    r->n_continuous = 0;
 }
 
 /* CDF of G/k for independent G ~ U[a,b], k ~ U[c,d]:
@@ -333,9 +334,15 @@ double orc_hf_median(const orc_ranges* r, int32_t n_act, int32_t n_inh) {
             double Gs = r->g_min + (r->g_max - r->g_min) * orc_hf_draw(n_act, n_inh, s, d++);
             double ks = r->k_min + (r->k_max - r->k_min) * orc_hf_draw(n_act, n_inh, s, d++);
             double T = M0 * (r->t_lo + (r->t_hi - r->t_lo) * orc_hf_draw(n_act, n_inh, s, d++));
-            int32_t span = r->n_max - r->n_min + 1;
-            int32_t off = (int32_t)floor(orc_hf_draw(n_act, n_inh, s, d++) * span);
-            if (off > span - 1) off = span - 1;
+            double un = orc_hf_draw(n_act, n_inh, s, d++), n;
+            if (r->n_continuous) {
+                n = (double)(float)((double)r->n_min + (double)(r->n_max - r->n_min) * un);
+            } else {
+                int32_t span = r->n_max - r->n_min + 1;
+                int32_t off = (int32_t)floor(un * span);
+                if (off > span - 1) off = span - 1;
+                n = (double)(r->n_min + off);
+            }
             double u = orc_hf_draw(n_act, n_inh, s, d++);
             double lam;
             if (e < n_act) {
@@ -344,7 +351,7 @@ double orc_hf_median(const orc_ranges* r, int32_t n_act, int32_t n_inh) {
                 double inv_lo = 1.0 / r->lam_inh_max, inv_hi = 1.0 / r->lam_inh_min;
                 lam = 1.0 / (inv_lo + (inv_hi - inv_lo) * u);
             }
-            double h = orc_shifted_hill(Gs / ks, T, (double)(r->n_min + off), lam);
+            double h = orc_shifted_hill(Gs / ks, T, n, lam);
             if (e < n_act && r->hf_act_over_lambda) h = h / lam;
             x *= h;
         }
@@ -358,8 +365,9 @@ double orc_hf_median(const orc_ranges* r, int32_t n_act, int32_t n_inh) {
 
 int orc_sample(int n_genes, int n_edges, const int32_t* src, const int32_t* dst, const int8_t* sign,
                const orc_ranges* r, uint64_t seed, int64_t set_begin, int64_t n_sets, int32_t n_ic,
-               float* G, float* k, float* T, float* lam, uint8_t* n, float* ic) {
+               float* G, float* k, float* T, float* lam, uint8_t* n, float* ic, float* nf) {
     if (n_genes < 1 || n_edges < 0 || n_sets < 0 || n_ic < 0) return -1;
+    if (r->n_continuous ? !nf : !n) return -1;
     if (r->method != ORC_UNIFORM && r->method != ORC_SOBOL && r->method != ORC_LHS) return -1;
     if (r->threshold_rule != ORC_T_PRIOR_MEDIAN && r->threshold_rule != ORC_T_HALF_FUNCTIONAL) return -1;
     const int64_t N = n_genes, E = n_edges;
@@ -395,12 +403,18 @@ int orc_sample(int n_genes, int n_edges, const int32_t* src, const int32_t* dst,
             /* Threshold: uniform in [t_lo, t_hi] times the source's scale. */
             double u = orc_unit(r, seed, p, base, 0, lhs_n);
             T[e * n_sets + j] = (float)(scale[e] * (r->t_lo + (r->t_hi - r->t_lo) * u));
-            /* Hill coefficient: integer, uniform over n_min..n_max. */
+            /* Hill coefficient: integer, uniform over n_min..n_max; or, in the
+             * continuous option, real and uniform on [n_min, n_max]. */
             u = orc_unit(r, seed, p, base + 1, 0, lhs_n);
-            int32_t span = r->n_max - r->n_min + 1;
-            int32_t off = (int32_t)floor(u * span);
-            if (off > span - 1) off = span - 1;
-            n[e * n_sets + j] = (uint8_t)(r->n_min + off);
+            if (r->n_continuous) {
+                nf[e * n_sets + j] = (float)((double)r->n_min + (double)(r->n_max - r->n_min) * u);
+            } else {
+                int32_t span = r->n_max - r->n_min + 1;
+                int32_t off = (int32_t)floor(u * span);
+                if (off > span - 1) off = span - 1;
+                n[e * n_sets + j] = (uint8_t)(r->n_min + off);
+                if (nf) nf[e * n_sets + j] = (float)(r->n_min + off);
+            }
             /* Fold change: activation uniform in its range; inhibition uniform
              * in the inverse range, then inverted. */
             u = orc_unit(r, seed, p, base + 2, 0, lhs_n);
@@ -452,7 +466,9 @@ void orc_rhs(const orc_problem* pb, int64_t p, int32_t divide, const double* x, 
             int j = pb->src[e];
             double B = x[j] > 0.0 ? x[j] : 0.0;
             double lam = pb->lam[e * P + p];
-            double hs = orc_shifted_hill(B, pb->T[e * P + p], (double)pb->n[e * P + p], lam);
+            /* Hill coefficient: the integer array, or the real-valued one when given. */
+            double n = pb->nf ? (double)pb->nf[e * P + p] : (double)pb->n[e * P + p];
+            double hs = orc_shifted_hill(B, pb->T[e * P + p], n, lam);
             if (pb->sign[e] > 0 && divide) hs = hs / lam; /* activating term over lambda */
             prod *= hs;
             ++e;

@@ -49,6 +49,7 @@ typedef struct {
     int32_t hf_samples;      /* Monte Carlo samples per in-degree class (> 0) */
     int32_t hf_act_over_lambda; /* activating terms over lambda in the estimate */
     int64_t lhs_total;       /* sets in the Latin hypercube (0: set_begin + n_sets) */
+    int32_t n_continuous;    /* 1: real Hill coefficients, uniform on [n_min, n_max] */
 } orc_ranges;
 
 enum { ORC_UNIFORM = 0, ORC_SOBOL = 1, ORC_LHS = 2 };
@@ -73,11 +74,14 @@ void orc_default_ranges(orc_ranges* r);
 double orc_gk_median(const orc_ranges* r);
 
 /* Sample sets [set_begin, set_begin+n_sets) into arrays of stride n_sets, and
- * n_ic initial-condition fractions ic[c*N + i] (ic may be NULL). */
+ * n_ic initial-condition fractions ic[c*N + i] (ic may be NULL).  Integer Hill
+ * coefficients go to n (required) and, when nf is not NULL, also to nf as
+ * floats; with r->n_continuous they are real, uniform on [n_min, n_max] (the
+ * same draw), go to nf (required) and n is not written. */
 int orc_sample(int n_genes, int n_edges, const int32_t* src_canon, const int32_t* dst_canon,
                const int8_t* sign_canon, const orc_ranges* r,
                uint64_t seed, int64_t set_begin, int64_t n_sets, int32_t n_ic,
-               float* G, float* k, float* T, float* lam, uint8_t* n, float* ic);
+               float* G, float* k, float* T, float* lam, uint8_t* n, float* ic, float* nf);
 
 typedef struct {
     double t0, t_end, rtol, atol, ss_atol, ss_rtol, h0;
@@ -112,6 +116,7 @@ typedef struct {
     int64_t n_sets; /* stride of the parameter arrays */
     const float* ic;
     int32_t n_ic;
+    const float* nf; /* real Hill coefficients [E][P], used instead of n when not NULL */
 } orc_problem;
 
 enum { ORC_CONVERGED = 0, ORC_T_END = 1, ORC_MAX_STEPS = 2, ORC_STEP_UNDERFLOW = 3, ORC_NONFINITE = 4 };

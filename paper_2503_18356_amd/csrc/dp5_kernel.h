@@ -87,7 +87,7 @@ struct Ops;
 template <>
 struct Ops<float> {
     using NType = float;
-    __device__ static float to_n(int n) { return (float)n; }
+    __device__ static float to_n(float n) { return n; }
     // Sources publish log2 of their level once per evaluation and edges keep
     // n log2 T, so an edge costs one fma, one exp2 and one reciprocal:
     //   factor = b + d / (1 + 2^(n log2 x - n log2 T)),
@@ -96,7 +96,7 @@ struct Ops<float> {
     // in the base-free form (the kernel body picks the form per shape).
     // x = 0 publishes -inf, giving the limit H^S = 1 in both forms.
     __device__ static float publish(float v) { return __builtin_amdgcn_logf(v > 0.0f ? v : 0.0f); }
-    __device__ static float edge_t(float T, int n) { return (float)n * __builtin_amdgcn_logf(T); }
+    __device__ static float edge_t(float T, float n) { return n * __builtin_amdgcn_logf(T); }
     __device__ static float hill(float lx, float nlT, float n, float b, float d) {
         const float r = __builtin_amdgcn_exp2f(__builtin_fmaf(n, lx, -nlT));
         return __builtin_fmaf(d, __builtin_amdgcn_rcpf(1.0f + r), b);
@@ -116,16 +116,27 @@ struct Ops<float> {
 template <>
 struct Ops<double> {
     using NType = int;
-    __device__ static int to_n(int n) { return n; }
-    // Sources publish their level, edges keep 1/T; (x/T)^n by squaring.
+    // An integer Hill coefficient is kept as itself; a real one as its FP32
+    // bits with the sign bit set (a negative int: n > 0 always).
+    __device__ static int to_n(float n) {
+        return (n == __builtin_floorf(n) && n <= 64.0f) ? (int)n
+                                                        : (int)(__builtin_bit_cast(uint32_t, n) | 0x80000000u);
+    }
+    // Sources publish their level, edges keep 1/T; (x/T)^n by squaring, or
+    // exp(n log(x/T)) for a real n.
     __device__ static double publish(double v) { return v > 0.0 ? v : 0.0; }
-    __device__ static double edge_t(double T, int) { return 1.0 / T; }
+    __device__ static double edge_t(double T, float) { return 1.0 / T; }
     __device__ static double hill(double xs, double invT, int n, double b, double d) {
         const double q = xs * invT;
         double r = 1.0, base = q;
-        for (int e = n; e > 0; e >>= 1) {
-            if (e & 1) r *= base;
-            base *= base;
+        if (n >= 0) {
+            for (int e = n; e > 0; e >>= 1) {
+                if (e & 1) r *= base;
+                base *= base;
+            }
+        } else {
+            const float nf = __builtin_bit_cast(float, (uint32_t)n & 0x7fffffffu);
+            r = ::exp((double)nf * ::log(q));
         }
         return fma(d, 1.0 / (1.0 + r), b);
     }
@@ -329,7 +340,7 @@ void dp5_kernel(LaunchArgs a) {
     uint32_t g_pe[GPL], g_pb[GPL];
 #pragma unroll
     for (int s = 0; s < EPL; ++s) {
-        e_xa[s] = sink; e_invT[s] = 0; e_d[s] = 0; e_n[s] = O::to_n(1);
+        e_xa[s] = sink; e_invT[s] = 0; e_d[s] = 0; e_n[s] = O::to_n(1.0f);
         if constexpr (!kUnitBase) e_b[s] = 1;
     }
     auto base_of = [&](int s) -> R {
@@ -475,7 +486,9 @@ void dp5_kernel(LaunchArgs a) {
             const int32_t* lane_edge = dp->lane_edge + r * stride;
             const float* Tp = dp->T + p;
             const float* Lp = dp->lam + p;
-            const uint8_t* Np = dp->n + p;
+            // Hill coefficients: real ones when given, else the integer array.
+            const float* NFp = dp->nf ? dp->nf + p : nullptr;
+            const uint8_t* Np = dp->nf ? nullptr : dp->n + p;
             // Only the loads are conditional: padding slots take T = lam = n = 1,
             // an inhibiting sign and the sink, which the same formulas turn
             // into a factor of exactly 1 (every array element is written on
@@ -484,8 +497,7 @@ void dp5_kernel(LaunchArgs a) {
             for (int s = 0; s < EPL; ++s) {
                 asm volatile("" ::: "memory");
                 const int pk = s < stride ? lane_edge[s] : -1;
-                float Tv = 1.0f, Lv = 1.0f;
-                int nv = 1;
+                float Tv = 1.0f, Lv = 1.0f, nv = 1.0f;
                 bool act = false;
                 uint32_t xa = sink;
                 if (pk >= 0) {
@@ -493,7 +505,7 @@ void dp5_kernel(LaunchArgs a) {
                     act = (pk & 0x8000) != 0;
                     Tv = Tp[e * P];
                     Lv = Lp[e * P];
-                    nv = Np[e * P];
+                    nv = NFp ? NFp[e * P] : (float)Np[e * P];
                     xa = (wave_elem + level_index(src)) * SZ;
                 }
                 e_xa[s] = xa;
@@ -501,7 +513,7 @@ void dp5_kernel(LaunchArgs a) {
                     // Activation: H^S = 1 + (lam - 1) / (1 + (T/x)^n), the
                     // exponent negated; inhibition: H^S = lam (1 + (1/lam - 1)
                     // / (1 + (x/T)^n)), the lam folded into the gene below.
-                    const float nn = act ? -(float)nv : (float)nv;
+                    const float nn = act ? -nv : nv;
                     e_n[s] = nn;
                     e_invT[s] = nn * __builtin_amdgcn_logf(Tv);
                     e_d[s] = act ? Lv - 1.0f : 1.0f / Lv - 1.0f;

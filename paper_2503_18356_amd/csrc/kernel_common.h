@@ -33,6 +33,7 @@ struct NetDesc {
     const float* T;
     const float* lam;
     const uint8_t* n;
+    const float* nf;           // real Hill coefficients [E][P], or nullptr: use n
     const float* ic;           // [n_ic][N]
     void* x_out;
     double* t_final;

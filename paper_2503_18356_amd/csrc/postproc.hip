@@ -538,10 +538,30 @@ bool codes_fit(int n_genes, int n_levels) {
     return true;
 }
 
+// The paper's steady-state flag per trajectory: 1 unless CONVERGED.
+__global__ void steady_flag_kernel(const int8_t* __restrict__ status, int64_t n, uint8_t* __restrict__ flag) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        flag[i] = status[i] == RAC_CONVERGED ? 0 : 1;
+}
+
 }  // namespace
 }  // namespace rac
 
 extern "C" {
+
+int32_t rac_not_steady_flag(int32_t status) { return status == RAC_CONVERGED ? 0 : 1; }
+
+rac_status rac_steady_flags(const int8_t* dev_status, int64_t n, uint8_t* dev_flag, void* hip_stream) {
+    using namespace rac;
+    if (n < 0) return fail(RAC_EINVAL, "rac_steady_flags: n < 0");
+    if (n == 0) return RAC_OK;
+    if (!dev_status || !dev_flag) return fail(RAC_EINVAL, "rac_steady_flags: NULL array");
+    hipLaunchKernelGGL(steady_flag_kernel, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream,
+                       dev_status, n, dev_flag);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(RAC_EDEVICE, std::string("rac_steady_flags: ") + hipGetErrorString(e));
+    return RAC_OK;
+}
 
 rac_status rac_normalize(const rac_topology* topo, const rac_params_view* p, int32_t n_ic, int32_t n_t,
                          const float* dev_x, float* dev_y, void* hip_stream) {

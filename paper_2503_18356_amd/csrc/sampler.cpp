@@ -86,7 +86,7 @@ bool ranges_ok(const rac_ranges& r) {
            (r.g_max > 0 || r.t_median > 0) &&
            (r.method == RAC_SAMPLE_UNIFORM || r.method == RAC_SAMPLE_SOBOL || r.method == RAC_SAMPLE_LHS) &&
            (r.threshold_rule == RAC_THRESHOLD_PRIOR_MEDIAN || r.threshold_rule == RAC_THRESHOLD_HALF_FUNCTIONAL) &&
-           r.hf_samples >= 1 && r.lhs_total >= 0;
+           r.hf_samples >= 1 && r.lhs_total >= 0 && (r.n_continuous == 0 || r.n_continuous == 1);
 }
 
 // ---- Sobol' direction numbers ---------------------------------------------
@@ -232,13 +232,20 @@ double hf_median(const rac_ranges& r, int na, int nh) {
             const double Gs = r.g_min + (r.g_max - r.g_min) * hf_draw(na, nh, s, d++);
             const double ks = r.k_min + (r.k_max - r.k_min) * hf_draw(na, nh, s, d++);
             const double T = M0 * (r.t_lo + (r.t_hi - r.t_lo) * hf_draw(na, nh, s, d++));
-            int32_t off = (int32_t)std::floor(hf_draw(na, nh, s, d++) * span);
-            if (off > span - 1) off = span - 1;
+            const double un = hf_draw(na, nh, s, d++);
+            double n;
+            if (r.n_continuous) {
+                n = (double)(float)((double)r.n_min + (double)(r.n_max - r.n_min) * un);
+            } else {
+                int32_t off = (int32_t)std::floor(un * span);
+                if (off > span - 1) off = span - 1;
+                n = (double)(r.n_min + off);
+            }
             const double u = hf_draw(na, nh, s, d++);
             const bool act = e < na;
             const double lam = act ? r.lam_act_min + (r.lam_act_max - r.lam_act_min) * u
                                    : 1.0 / (inv_lo + (inv_hi - inv_lo) * u);
-            double h = shifted_hill(Gs / ks, T, (double)(r.n_min + off), lam);
+            double h = shifted_hill(Gs / ks, T, n, lam);
             if (act && r.hf_act_over_lambda) h = h / lam;
             x *= h;
         }
@@ -339,6 +346,7 @@ void rac_default_ranges(rac_ranges* r) {
     r->hf_samples = 65536;
     r->hf_act_over_lambda = 1;
     r->lhs_total = 0;
+    r->n_continuous = 0;
 }
 
 rac_status rac_sample_params(const rac_topology* topo, const rac_ranges* ranges, uint64_t seed,
@@ -351,14 +359,15 @@ rac_status rac_sample_params(const rac_topology* topo, const rac_ranges* ranges,
         return fail(RAC_EINVAL, "rac_sample_params: negative count or offset");
     if (out->n_sets != n_sets) return fail(RAC_EINVAL, "rac_sample_params: out->n_sets != n_sets");
     const int64_t N = topo->n_genes, E = topo->n_edges;
-    if (n_sets > 0 && (!out->G || !out->k || (E > 0 && (!out->T || !out->lam || !out->n))))
-        return fail(RAC_EINVAL, "rac_sample_params: NULL parameter array");
     rac_ranges r;
     if (ranges)
         r = *ranges;
     else
         rac_default_ranges(&r);
     if (!rac::ranges_ok(r)) return fail(RAC_EINVAL, "rac_sample_params: invalid ranges");
+    if (n_sets > 0 && (!out->G || !out->k ||
+                       (E > 0 && (!out->T || !out->lam || (r.n_continuous ? !out->nf : !out->n)))))
+        return fail(RAC_EINVAL, "rac_sample_params: NULL parameter array");
     rac::SampleTables tb;
     rac_status st = rac::make_sample_tables(topo, r, seed, set_begin, n_sets, n_ic, &tb);
     if (st != RAC_OK) return st;
@@ -375,9 +384,14 @@ rac_status rac_sample_params(const rac_topology* topo, const rac_ranges* ranges,
             const double ut = rac::unit(tb, seed, p, slot, 0);
             out->T[e * n_sets + j] = (float)(tb.scale[(size_t)e] * (r.t_lo + (r.t_hi - r.t_lo) * ut));
             const double un = rac::unit(tb, seed, p, slot + 1, 0);
-            int32_t k = (int32_t)std::floor(un * n_span);
-            if (k > n_span - 1) k = n_span - 1;
-            out->n[e * n_sets + j] = (uint8_t)(r.n_min + k);
+            if (r.n_continuous) {
+                out->nf[e * n_sets + j] = (float)((double)r.n_min + (double)(r.n_max - r.n_min) * un);
+            } else {
+                int32_t k = (int32_t)std::floor(un * n_span);
+                if (k > n_span - 1) k = n_span - 1;
+                out->n[e * n_sets + j] = (uint8_t)(r.n_min + k);
+                if (out->nf) out->nf[e * n_sets + j] = (float)(r.n_min + k);
+            }
             const double ul = rac::unit(tb, seed, p, slot + 2, 0);
             double lam;
             if (topo->sign[e] > 0)

@@ -52,7 +52,9 @@ struct SampleArgs {
     double g_min, g_span, k_min, k_span, la_min, la_span, inv_lo, inv_span;
     double M, t_lo, t_span;
     int32_t n_min, n_span;
-    float *G, *k, *T, *lam, *ic;
+    int32_t n_continuous;
+    double nc_span;  // n_max - n_min (continuous option)
+    float *G, *k, *T, *lam, *ic, *nf;
     uint8_t* n;
     // Generator tables (device; NULL for uniform draws with one threshold scale).
     int32_t method;
@@ -118,9 +120,14 @@ __global__ __launch_bounds__(256) void sample_kernel(SampleArgs a) {
             if (which == 0) {
                 a.T[e * a.n_sets + j] = (float)__dmul_rn(a.scale ? a.scale[e] : a.M, lin(a.t_lo, a.t_span, u));
             } else if (which == 1) {
-                int32_t kk = (int32_t)floor(__dmul_rn(u, (double)a.n_span));
-                if (kk > a.n_span - 1) kk = a.n_span - 1;
-                a.n[e * a.n_sets + j] = (uint8_t)(a.n_min + kk);
+                if (a.n_continuous) {
+                    a.nf[e * a.n_sets + j] = (float)lin((double)a.n_min, a.nc_span, u);
+                } else {
+                    int32_t kk = (int32_t)floor(__dmul_rn(u, (double)a.n_span));
+                    if (kk > a.n_span - 1) kk = a.n_span - 1;
+                    a.n[e * a.n_sets + j] = (uint8_t)(a.n_min + kk);
+                    if (a.nf) a.nf[e * a.n_sets + j] = (float)(a.n_min + kk);
+                }
             } else {
                 const double l = a.sign[e] > 0 ? lin(a.la_min, a.la_span, u)
                                                : __ddiv_rn(1.0, lin(a.inv_lo, a.inv_span, u));
@@ -157,14 +164,15 @@ extern "C" rac_status rac_sample_params_device(const rac_topology* topo, const r
         return fail(RAC_EINVAL, "rac_sample_params_device: negative count or offset");
     if (dev_out->n_sets != n_sets) return fail(RAC_EINVAL, "rac_sample_params_device: out->n_sets != n_sets");
     const int64_t N = topo->n_genes, E = topo->n_edges;
-    if (n_sets > 0 && (!dev_out->G || !dev_out->k || (E > 0 && (!dev_out->T || !dev_out->lam || !dev_out->n))))
-        return fail(RAC_EINVAL, "rac_sample_params_device: NULL parameter array");
     rac_ranges r;
     if (ranges)
         r = *ranges;
     else
         rac_default_ranges(&r);
     if (!sample_ranges_ok(r)) return fail(RAC_EINVAL, "rac_sample_params_device: invalid ranges");
+    if (n_sets > 0 && (!dev_out->G || !dev_out->k ||
+                       (E > 0 && (!dev_out->T || !dev_out->lam || (r.n_continuous ? !dev_out->nf : !dev_out->n)))))
+        return fail(RAC_EINVAL, "rac_sample_params_device: NULL parameter array");
     if (n_sets == 0 && (n_ic == 0 || !dev_ic_frac)) return RAC_OK;
     const DevicePlan* dp = nullptr;
     rac_status st = get_device_plan(topo, 1, &dp);  // carries the device copy of the signs
@@ -191,6 +199,9 @@ extern "C" rac_status rac_sample_params_device(const rac_topology* topo, const r
     a.t_span = r.t_hi - r.t_lo;
     a.n_min = r.n_min;
     a.n_span = r.n_max - r.n_min + 1;
+    a.n_continuous = r.n_continuous;
+    a.nc_span = (double)(r.n_max - r.n_min);
+    a.nf = dev_out->nf;
     a.G = dev_out->G;
     a.k = dev_out->k;
     a.T = dev_out->T;

@@ -176,6 +176,7 @@ rac_status rac_server_submit(rac_server* s, const rac_topology* topo, const rac_
     d.T = dev_params->T;
     d.lam = dev_params->lam;
     d.n = dev_params->n;
+    d.nf = dev_params->nf;
     d.ic = dev_ic;
     d.x_out = dev_x_out;
     if (dev_info) {

@@ -165,7 +165,7 @@ rac_status check_item(const rac_topology* topo, const rac_params_view* p, const 
     if (p->n_sets < 0) return fail(RAC_EINVAL, w + ": n_sets < 0");
     if (n_ic < 1) return fail(RAC_EINVAL, w + ": n_ic < 1");
     if (p->n_sets > 0) {
-        if (!p->G || !p->k || (topo->n_edges > 0 && (!p->T || !p->lam || !p->n)))
+        if (!p->G || !p->k || (topo->n_edges > 0 && (!p->T || !p->lam || (!p->n && !p->nf))))
             return fail(RAC_EINVAL, w + ": NULL parameter array");
         if (!ic) return fail(RAC_EINVAL, w + ": NULL initial conditions");
         if (!x_out) return fail(RAC_EINVAL, w + ": NULL x_out");
@@ -234,6 +234,7 @@ rac_status launch_group(const std::vector<Job>& jobs, int lpt, const rac_solver_
         d.T = j.params.T;
         d.lam = j.params.lam;
         d.n = j.params.n;
+        d.nf = j.params.nf;
         d.ic = j.ic;
         d.x_out = j.x_out;
         d.t_final = j.info.t_final;

@@ -41,12 +41,12 @@ class _Ranges(C.Structure):
                 ("n_max", C.c_int32), ("t_lo", C.c_double), ("t_hi", C.c_double),
                 ("t_median", C.c_double), ("method", C.c_int32), ("threshold_rule", C.c_int32),
                 ("hf_samples", C.c_int32), ("hf_act_over_lambda", C.c_int32),
-                ("lhs_total", C.c_int64)]
+                ("lhs_total", C.c_int64), ("n_continuous", C.c_int32)]
 
 
 class _ParamsView(C.Structure):
     _fields_ = [("G", C.c_void_p), ("k", C.c_void_p), ("T", C.c_void_p), ("lam", C.c_void_p),
-                ("n", C.c_void_p), ("n_sets", C.c_int64)]
+                ("n", C.c_void_p), ("n_sets", C.c_int64), ("nf", C.c_void_p)]
 
 
 class _Opts(C.Structure):
@@ -132,6 +132,10 @@ def lib():
         L.rac_server_done_counts.restype = C.c_int
         L.rac_server_info.argtypes = [vp, vp, vp, vp, vp]
         L.rac_server_info.restype = C.c_int
+        L.rac_not_steady_flag.argtypes = [i32]
+        L.rac_not_steady_flag.restype = i32
+        L.rac_steady_flags.argtypes = [vp, i64, vp, vp]
+        L.rac_steady_flags.restype = C.c_int
         L.rac_normalize.argtypes = [vp, C.POINTER(_ParamsView), i32, i32, vp, vp, vp]
         L.rac_normalize.restype = C.c_int
         L.rac_level_thresholds.argtypes = [vp, i64, i32, vp, i32, i32, vp, vp, vp]
@@ -250,6 +254,7 @@ class Ranges:
     hf_samples: int = 65536
     hf_act_over_lambda: int = 1
     lhs_total: int = 0
+    n_continuous: int = 0       # 1: real Hill coefficients on [n_min, n_max], in nf
 
     def c(self) -> _Ranges:
         return _Ranges(*[getattr(self, f[0]) for f in _Ranges._fields_])
@@ -264,6 +269,7 @@ class HostParams:
     lam: np.ndarray
     n: np.ndarray
     ic: np.ndarray
+    nf: np.ndarray | None = None   # real Hill coefficients (f32), used instead of n
 
     @property
     def n_sets(self) -> int:
@@ -271,19 +277,22 @@ class HostParams:
 
     def to_device(self, device="cuda"):
         import torch
-        return DeviceParams(*[torch.from_numpy(np.ascontiguousarray(getattr(self, f.name))).to(device)
+        return DeviceParams(*[None if getattr(self, f.name) is None else
+                              torch.from_numpy(np.ascontiguousarray(getattr(self, f.name))).to(device)
                               for f in fields(self)])
 
 
 @dataclass
 class DeviceParams:
-    """torch tensors on the GPU: G, k [N][P]; T, lam [E][P] f32; n [E][P] u8; ic [n_ic][N]."""
+    """torch tensors on the GPU: G, k [N][P]; T, lam [E][P] f32; n [E][P] u8; ic [n_ic][N];
+    nf [E][P] f32 real Hill coefficients or None."""
     G: object
     k: object
     T: object
     lam: object
     n: object
     ic: object
+    nf: object = None
 
     @property
     def n_sets(self) -> int:
@@ -295,7 +304,8 @@ class DeviceParams:
 
     def view(self) -> _ParamsView:
         return _ParamsView(self.G.data_ptr(), self.k.data_ptr(), self.T.data_ptr(),
-                           self.lam.data_ptr(), self.n.data_ptr(), self.n_sets)
+                           self.lam.data_ptr(), None if self.n is None else self.n.data_ptr(), self.n_sets,
+                           None if self.nf is None else self.nf.data_ptr())
 
 
 def sample_params(topo: Topology, seed: int, n_sets: int, n_ic: int, set_begin: int = 0,
@@ -307,28 +317,34 @@ def sample_params(topo: Topology, seed: int, n_sets: int, n_ic: int, set_begin: 
     lam = np.zeros((E, P), np.float32)
     n = np.zeros((E, P), np.uint8)
     ic = np.zeros((n_ic, N), np.float32)
-    v = _ParamsView(G.ctypes.data, k.ctypes.data, T.ctypes.data, lam.ctypes.data, n.ctypes.data, P)
-    rr = (ranges or Ranges()).c()
+    rg = ranges or Ranges()
+    nf = np.zeros((E, P), np.float32) if rg.n_continuous else None
+    v = _ParamsView(G.ctypes.data, k.ctypes.data, T.ctypes.data, lam.ctypes.data, n.ctypes.data, P,
+                    None if nf is None else nf.ctypes.data)
+    rr = rg.c()
     _check(lib().rac_sample_params(topo.handle, C.byref(rr), C.c_uint64(seed & (2**64 - 1)),
                                    set_begin, P, n_ic, C.byref(v), ic.ctypes.data))
-    return HostParams(G, k, T, lam, n, ic)
+    return HostParams(G, k, T, lam, n, ic, nf)
 
 
-def alloc_params(topo: Topology, n_sets: int, n_ic: int, device="cuda") -> DeviceParams:
+def alloc_params(topo: Topology, n_sets: int, n_ic: int, device="cuda",
+                 n_continuous: bool = False) -> DeviceParams:
     import torch
     N, E, P = topo.n_genes, topo.n_edges, int(n_sets)
     f = lambda *sh: torch.empty(sh, dtype=torch.float32, device=device)
     return DeviceParams(f(N, P), f(N, P), f(E, P), f(E, P),
-                        torch.empty((E, P), dtype=torch.uint8, device=device), f(n_ic, N))
+                        torch.empty((E, P), dtype=torch.uint8, device=device), f(n_ic, N),
+                        f(E, P) if n_continuous else None)
 
 
 def sample_params_device(topo: Topology, seed: int, n_sets: int, n_ic: int, set_begin: int = 0,
                          ranges: Ranges | None = None, out: DeviceParams | None = None,
                          stream=None) -> DeviceParams:
     """rac_sample_params_device: the same draws as sample_params, on the GPU."""
-    out = out or alloc_params(topo, n_sets, n_ic)
+    rg = ranges or Ranges()
+    out = out or alloc_params(topo, n_sets, n_ic, n_continuous=bool(rg.n_continuous))
     v = out.view()
-    rr = (ranges or Ranges()).c()
+    rr = rg.c()
     _check(lib().rac_sample_params_device(topo.handle, C.byref(rr), C.c_uint64(seed & (2**64 - 1)),
                                           set_begin, int(n_sets), n_ic, C.byref(v),
                                           out.ic.data_ptr(), _stream_ptr(stream)))
@@ -496,6 +512,20 @@ NO_STATE = -1
 
 def _ptr(t):
     return None if t is None else t.data_ptr()
+
+
+def not_steady_flag(status: int) -> int:
+    """The paper's steady-state flag of one status: 0 if CONVERGED, else 1."""
+    return int(lib().rac_not_steady_flag(int(status)))
+
+
+def steady_flags(status, out=None, stream=None):
+    """rac_steady_flags: the paper's flag (u8, 1 = no steady state) for every
+    trajectory of a device status array."""
+    import torch
+    out = out if out is not None else torch.empty(status.numel(), dtype=torch.uint8, device=status.device)
+    _check(lib().rac_steady_flags(status.data_ptr(), status.numel(), out.data_ptr(), _stream_ptr(stream)))
+    return out
 
 
 def normalize(topo: Topology, params: DeviceParams, x, n_t: int = 1, out=None, stream=None):

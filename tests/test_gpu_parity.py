@@ -32,14 +32,15 @@ def say(*a):
 class Case:
     """A network with parameters sampled on both sides."""
 
-    def __init__(self, topo, seed, n_sets, n_ic):
+    def __init__(self, topo, seed, n_sets, n_ic, **ranges):
         self.topo = topo
         self.T = rp.Topology.from_inputs(topo)
         self.net = oracle.canonicalize(topo.n_genes, topo.src, topo.dst, topo.sign)
-        self.hp = rp.sample_params(self.T, seed, n_sets, n_ic)
-        self.op = oracle.sample(self.net, seed, n_sets, n_ic)
-        for f in ("G", "k", "T", "lam", "n", "ic"):
-            assert np.array_equal(getattr(self.hp, f), getattr(self.op, f))
+        self.hp = rp.sample_params(self.T, seed, n_sets, n_ic, ranges=rp.Ranges(**ranges))
+        self.op = oracle.sample(self.net, seed, n_sets, n_ic, ranges=oracle.Ranges(**ranges))
+        for f in ("G", "k", "T", "lam", "n", "ic", "nf"):
+            a, b = getattr(self.hp, f), getattr(self.op, f)
+            assert (a is None and b is None) or np.array_equal(a, b), f
         self.dp = self.hp.to_device()
         self.n_ic = n_ic
         self.n_traj = n_sets * n_ic
@@ -119,6 +120,41 @@ def test_every_lane_count(topo, prec):
     for lanes in (1, 2, 4, 8, 16, 32, 64):
         if case.T.lanes_supported(lanes, prec):
             case.check(opts_for(prec, lanes_per_traj=lanes), label=f"lanes={lanes}")
+
+
+@pytest.mark.parametrize("prec", [rp.FP32, rp.FP64])
+@pytest.mark.parametrize("topo", [inputs.toggle_switch_self_activation(), inputs.erdos_renyi(10, 25, 1002),
+                                  inputs.dense_core(1004)], ids=["TSSA", "ER10", "core22"])
+def test_real_hill_coefficients(topo, prec):
+    # Eq. 2 with real exponents n ~ U[1, 6] (the continuous reading of Table
+    # 1's range) through the nf array of the parameter view.
+    case = Case(topo, 61, 400, 5, n_continuous=1)
+    assert case.hp.nf is not None and np.mean(case.hp.nf != np.round(case.hp.nf)) > 0.99
+    case.check(opts_for(prec, ss_rtol=1e-5), label="real n")
+
+
+def test_real_hill_time_series():
+    case = Case(inputs.dense_core(1004), 62, 60, 5, n_continuous=1)
+    tk = np.linspace(0.0, 100.0, 101)
+    opts = opts_for(rp.FP32)
+    out = rp.integrate(case.T, case.dp, tk, opts)
+    torch.cuda.synchronize()
+    ref = oracle.time_series(case.net, case.op, tk, case.oracle_opts(opts), n_threads=THREADS)
+    err, _ = parity.compare_series(case.op, np.arange(case.n_traj), out.x.cpu().numpy(), ref.x, case.n_ic)
+    say("    real n series, max normalised error", float(err.max()))
+    assert err.max() <= parity.TOL
+
+
+def test_steady_flags():
+    # The paper's flag (1 = no steady state) for every trajectory, on the device.
+    case = Case(inputs.erdos_renyi(10, 25, 1002), 63, 200, 5)
+    out = case.gpu(opts_for(rp.FP32, t_end=60.0))
+    flags = rp.steady_flags(out.status)
+    torch.cuda.synchronize()
+    st = out.status.cpu().numpy()
+    assert set(np.unique(st)) == {rp.CONVERGED, rp.T_END}
+    assert np.array_equal(flags.cpu().numpy(), (st != rp.CONVERGED).astype(np.uint8))
+    assert [rp.not_steady_flag(s) for s in range(5)] == [0, 1, 1, 1, 1]
 
 
 def test_time_series_dense_core():

@@ -48,6 +48,17 @@ def test_device_sampler_custom_ranges():
         assert np.array_equal(getattr(h, f), getattr(d, f).cpu().numpy()), f
 
 
+@pytest.mark.parametrize("method", [rp.SAMPLE_UNIFORM, rp.SAMPLE_SOBOL])
+def test_device_sampler_continuous_hill(method):
+    T = rp.Topology.from_inputs(inputs.dense_core(1004))
+    r = rp.Ranges(method=method, n_continuous=1)
+    h = rp.sample_params(T, 19, 2000, 3, ranges=r)
+    d = rp.sample_params_device(T, 19, 2000, 3, ranges=r)
+    torch.cuda.synchronize()
+    for f in ("G", "k", "T", "lam", "nf", "ic"):
+        assert np.array_equal(getattr(h, f), getattr(d, f).cpu().numpy()), f
+
+
 @pytest.mark.parametrize("rule", [rp.PRIOR_MEDIAN, rp.HALF_FUNCTIONAL])
 @pytest.mark.parametrize("method", [rp.SAMPLE_UNIFORM, rp.SAMPLE_SOBOL, rp.SAMPLE_LHS])
 def test_device_sampler_all_generators(method, rule):

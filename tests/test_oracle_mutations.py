@@ -93,6 +93,13 @@ MUTATIONS = [
      "s->o->ss_rtol * fabs(x[i])", [lambda: scipy_pins.test_scaled_steady_stop_closed_form((0.2,))]),
     ("steady test drops the relative term", "s->o->ss_rtol * (double)s->pb->k[i * P + s->p] * fabs(x[i])",
      "0.0 * fabs(x[i])", [lambda: scipy_pins.test_scaled_steady_stop_closed_form((0.15, 0.6, 0.35))]),
+    ("real Hill coefficient ignored",
+     "double n = pb->nf ? (double)pb->nf[e * P + p] : (double)pb->n[e * P + p];",
+     "double n = (double)pb->n[e * P + p];", [pins.test_real_hill_half_point]),
+    ("real Hill coefficient range",
+     "nf[e * n_sets + j] = (float)((double)r->n_min + (double)(r->n_max - r->n_min) * u);",
+     "nf[e * n_sets + j] = (float)((double)r->n_min + (double)(r->n_max) * u);",
+     [pins.test_real_hill_sampler_uses_the_integer_draw]),
     ("half-functional activation not over lambda", "if (e < n_act && r->hf_act_over_lambda) h = h / lam;",
      "", [lambda: sampler.test_half_functional_median_matches_independent_monte_carlo(1, 0)]),
 ]

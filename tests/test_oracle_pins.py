@@ -516,3 +516,74 @@ def test_toggle_switch_mostly_exclusive_states():
     per_set = states.reshape(P, 10)
     mono = np.mean([len(set(r)) == 1 for r in per_set])
     assert mono > 0.5
+
+
+# --------------------------------------------------------------------------
+# Real (non-integer) Hill coefficients (Eq. 2 with a real exponent; Table 1
+# gives the range 1-6 without a type).
+# --------------------------------------------------------------------------
+def _with_nf(prm, nf):
+    return oracle.Params(prm.G, prm.k, prm.T, prm.lam, prm.n, prm.ic,
+                         np.asarray(nf, np.float32).reshape(prm.n.shape))
+
+
+def test_real_hill_half_point():
+    # B = T * 3^(1/n) gives (B/T)^n = 3 for any real n: H = (1 + 3 lam)/4.
+    net = net_of(inputs.Topology(2, np.array([0], np.int32), np.array([1], np.int32),
+                                 np.array([-1], np.int8)))
+    lam = float(np.float32(0.25))
+    for n in (1.5, 2.75, 4.2):
+        nf = float(np.float32(n))
+        T = 2.0
+        B = T * 3 ** (1 / nf)
+        prm = _with_nf(hand_params(net, G=[1.0, 2.0], k=[0.5, 0.5], T=[T], lam=[lam], n=[1]), [nf])
+        f = oracle.rhs(net, prm, 0, [B, 0.0])
+        assert f[1] / 2.0 == pytest.approx((1 + 3 * lam) / 4, rel=1e-12)
+
+
+def test_real_hill_equal_to_integer_when_integral():
+    # nf holding the integer coefficients gives bit-identical trajectories.
+    net = net_of(inputs.erdos_renyi(6, 12, 8))
+    prm = oracle.sample(net, 3, 20, 3)
+    a = oracle.steady_states(net, prm, oracle.Opts(ss_rtol=1e-5), n_threads=2)
+    b = oracle.steady_states(net, _with_nf(prm, prm.n.astype(np.float32)), oracle.Opts(ss_rtol=1e-5),
+                             n_threads=2)
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.n_acc, b.n_acc)
+
+
+def test_real_hill_self_activation_fixed_point_by_bisection():
+    # G (T^n + lam x^n) / (lam (T^n + x^n)) - k x with n = 1.7: the positive
+    # root found by bisection on a bracket where g changes sign once.
+    net = net_of(inputs.Topology(1, np.array([0], np.int32), np.array([0], np.int32),
+                                 np.array([1], np.int8)))
+    G, k, T, lam, n = (float(np.float32(v)) for v in (40.0, 0.5, 30.0, 6.0, 1.7))
+    prm = _with_nf(hand_params(net, G=[G], k=[k], T=[T], lam=[lam], n=[1], ic=[[0.95]]), [n])
+    g = lambda x: G * (T ** n + lam * x ** n) / (lam * (T ** n + x ** n)) - k * x
+    # High branch: g > 0 at 60, g < 0 at G/k.
+    lo, hi = 60.0, G / k
+    assert g(lo) > 0 > g(hi)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if g(mid) > 0:
+            lo = mid
+        else:
+            hi = mid
+    res = oracle.steady_states(net, prm, TIGHT)
+    assert res.status[0] == oracle.CONVERGED
+    assert res.x[0, 0] == pytest.approx(lo, rel=1e-8)
+
+
+def test_real_hill_sampler_uses_the_integer_draw():
+    # The continuous option maps the same uniform draw u to 1 + 5u that the
+    # integer option maps to 1 + floor(6u), so floor(6 (nf - 1) / 5) = n - 1
+    # away from the stratum edges; and nf is uniform on [1, 6].
+    net = net_of(inputs.erdos_renyi(10, 25, 1002))
+    a = oracle.sample(net, 17, 20000, 1)
+    b = oracle.sample(net, 17, 20000, 1, ranges=oracle.Ranges(n_continuous=1))
+    u = (b.nf.astype(np.float64) - 1.0) / 5.0
+    interior = np.abs(u * 6 - np.round(u * 6)) > 1e-5
+    assert np.array_equal(np.floor(6 * u[interior]).astype(np.int64) + 1, a.n[interior].astype(np.int64))
+    v = np.sort(b.nf.ravel().astype(np.float64))
+    ks = np.max(np.abs(np.arange(1, v.size + 1) / v.size - (v - 1) / 5))
+    assert ks < 1.95 / math.sqrt(v.size)
+    assert np.array_equal(a.G, b.G) and np.array_equal(a.T, b.T) and np.array_equal(a.lam, b.lam)

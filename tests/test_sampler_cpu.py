@@ -27,10 +27,26 @@ def test_host_sampler_bit_exact_with_oracle(topo, method, rule):
             assert np.array_equal(getattr(h, f), getattr(o, f)), f
 
 
+@pytest.mark.parametrize("method", [rp.SAMPLE_UNIFORM, rp.SAMPLE_SOBOL])
+def test_host_sampler_continuous_hill_bit_exact_with_oracle(method):
+    # Real Hill coefficients uniform on [n_min, n_max] (Table 1's range, no
+    # type given), with the half-functional rule drawing them the same way.
+    topo = inputs.erdos_renyi(10, 25, 1002)
+    T = rp.Topology.from_inputs(topo)
+    net = oracle.canonicalize(topo.n_genes, topo.src, topo.dst, topo.sign)
+    kw = dict(method=method, threshold_rule=rp.HALF_FUNCTIONAL, hf_samples=2048, n_continuous=1)
+    h = rp.sample_params(T, 55, 300, 4, ranges=rp.Ranges(**kw))
+    o = oracle.sample(net, 55, 300, 4, ranges=oracle.Ranges(**kw))
+    for f in ("G", "k", "T", "lam", "nf", "ic"):
+        assert np.array_equal(getattr(h, f), getattr(o, f)), f
+    assert h.nf.min() >= 1.0 and h.nf.max() <= 6.0
+    assert np.mean(h.nf != np.round(h.nf)) > 0.99
+
+
 def test_bad_sampler_choices_are_rejected():
     T = rp.Topology.from_inputs(inputs.toggle_switch())
     for kw in (dict(method=3), dict(threshold_rule=2), dict(hf_samples=0),
-               dict(method=rp.SAMPLE_LHS, lhs_total=10)):
+               dict(method=rp.SAMPLE_LHS, lhs_total=10), dict(n_continuous=2)):
         with pytest.raises(rp.RacError) as e:
             rp.sample_params(T, 1, 20, 1, ranges=rp.Ranges(**kw))
         assert e.value.code == rp.EINVAL
