@@ -282,6 +282,24 @@ rac_status rac_steady_states(const rac_topology* topo, const rac_params_view* de
                              const float* dev_ic, int32_t n_ic, const rac_solver_opts* opts,
                              void* dev_x_out, const rac_traj_info* dev_info, void* hip_stream);
 
+/* rac_steady_states for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results, bit for bit, but no
+ * device allocation or free.  The queue counter and the network descriptor
+ * live in a library-owned device scratch array of 1024 bytes per GPU (the
+ * counter and one descriptor: one network per call), kept until the process
+ * ends and cleared by a kernel at the start of every call.  Calls that
+ * overlap on one GPU (concurrent streams or threads) share that scratch and
+ * race: order them on one stream.  The network's lane plan for the lane count
+ * the options select must already be on the current device, which any
+ * earlier rac_steady_states call with the same options leaves there.
+ * EINVAL as rac_steady_states, and when the lane plan is not on the device;
+ * EUNSUPPORTED as rac_steady_states; EDEVICE if the scratch address cannot be
+ * found. */
+rac_status rac_steady_states_noalloc(const rac_topology* topo, const rac_params_view* dev_params,
+                                     const float* dev_ic, int32_t n_ic, const rac_solver_opts* opts,
+                                     void* dev_x_out, const rac_traj_info* dev_info, void* hip_stream);
+
 /* Time series at host_t_out[0..n_t) (strictly increasing, >= t0; Sec. 2.1.3):
  * integrates to the last output time; each output is the DP5 continuous
  * extension (Hairer, Norsett, Wanner I, Sec. II.6) at that time.

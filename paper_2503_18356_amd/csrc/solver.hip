@@ -72,6 +72,15 @@ static hipStream_t lib_stream(int dev) {
     return s;
 }
 
+// The device copy of a plan made earlier on the current device, without
+// building or uploading anything (nullptr if there is none).
+static const DevicePlan* find_device_plan(const rac_topology* t, int lpt, int dev) {
+    std::lock_guard<std::mutex> lk(t->mu);
+    for (auto& d : t->dev_plans)
+        if (d.device == dev && d.lpt == lpt) return &d;
+    return nullptr;
+}
+
 rac_status get_device_plan(const rac_topology* t, int lpt, const DevicePlan** out) {
     int dev = 0;
     RAC_HIP(hipGetDevice(&dev), "hipGetDevice");
@@ -213,16 +222,33 @@ std::map<std::tuple<int, const void*>, int>& occupancy_cache() {
 
 // Launch one persistent kernel over the given networks (all with lane count
 // lpt) in a shared work queue.
+// With fixed_block (a single steady-state network only), the queue counter
+// and the network descriptor go to that device block instead of a per-call
+// allocation, and the lane plan must already be on the device: nothing is
+// allocated.
 rac_status launch_group(const std::vector<Job>& jobs, int lpt, const rac_solver_opts* o, bool ts,
-                        const double* host_t_out, int32_t n_t, hipStream_t stream) {
+                        const double* host_t_out, int32_t n_t, hipStream_t stream,
+                        char* fixed_block = nullptr) {
     int epl = 0, gpl = 0, max_n = 0;
     int64_t total = 0;
     std::vector<NetDesc> descs;
+    if (fixed_block && (ts || jobs.size() != 1))
+        return fail(RAC_EINVAL, "launch without allocation: one steady-state network only");
+    int cur_dev = 0;
+    RAC_HIP(hipGetDevice(&cur_dev), "hipGetDevice");
     for (const Job& j : jobs) {
-        const LanePlan* lp = get_plan(j.topo, lpt);
         const DevicePlan* dp = nullptr;
-        rac_status st = get_device_plan(j.topo, lpt, &dp);
-        if (st != RAC_OK) return st;
+        if (fixed_block) {
+            dp = find_device_plan(j.topo, lpt, cur_dev);
+            if (!dp)
+                return fail(RAC_EINVAL, "the network's lane plan for " + std::to_string(lpt) +
+                                            " lanes is not on this device yet: solve it once with "
+                                            "rac_steady_states (same options) before the call without allocation");
+        } else {
+            rac_status st = get_device_plan(j.topo, lpt, &dp);
+            if (st != RAC_OK) return st;
+        }
+        const LanePlan* lp = get_plan(j.topo, lpt);
         NetDesc d;
         std::memset(&d, 0, sizeof(d));
         d.lane_edge = dp->lane_edge;
@@ -298,8 +324,8 @@ rac_status launch_group(const std::vector<Job>& jobs, int lpt, const rac_solver_
     const size_t off_nets = 256;
     const size_t off_t = off_nets + (descs.size() * sizeof(NetDesc) + 255) / 256 * 256;
     const size_t bytes = off_t + (ts ? sizeof(double) * n_t : 0);
-    void* blk = nullptr;
-    RAC_HIP(hipMallocAsync(&blk, bytes, stream), "hipMallocAsync");
+    void* blk = fixed_block;
+    if (!fixed_block) RAC_HIP(hipMallocAsync(&blk, bytes, stream), "hipMallocAsync");
     char* b = (char*)blk;
     a.counter = (unsigned long long*)b;
     a.nets = (const NetDesc*)(b + off_nets);
@@ -316,7 +342,7 @@ rac_status launch_group(const std::vector<Job>& jobs, int lpt, const rac_solver_
     RAC_HIP(hipGetLastError(), "setup_launch");
     void* args[] = {&a};
     RAC_HIP(hipLaunchKernel(ke->fn, dim3(grid), dim3(kBlock), args, 0, stream), "dp5 kernel launch");
-    RAC_HIP(hipFreeAsync(blk, stream), "hipFreeAsync");
+    if (!fixed_block) RAC_HIP(hipFreeAsync(blk, stream), "hipFreeAsync");
     return RAC_OK;
 }
 
@@ -387,6 +413,33 @@ rac_status run_jobs(std::vector<Job>& jobs, const rac_solver_opts* o, bool ts,
     return st;
 }
 
+// Device scratch of the call without allocation: the queue counter in the
+// first 256 bytes, the network descriptor after it.  Each device holds its
+// own copy for the life of the process; in host code the array's name is
+// only a stand-in, so its device address is looked up once per device and
+// used everywhere instead.
+constexpr size_t kNoAllocScratchBytes = 1024;
+static_assert(256 + sizeof(NetDesc) <= kNoAllocScratchBytes, "scratch holds the counter and one descriptor");
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+rac_status scratch_address(int dev, char** out) {
+    static std::mutex m;
+    static std::map<int, char*> addr;
+    std::lock_guard<std::mutex> lk(m);
+    auto it = addr.find(dev);
+    if (it != addr.end()) {
+        *out = it->second;
+        return RAC_OK;
+    }
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(RAC_EDEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+    addr[dev] = (char*)p;
+    *out = (char*)p;
+    return RAC_OK;
+}
+
 }  // namespace
 
 rac_status check_opts_public(const rac_solver_opts* o, const char* who) { return check_opts(o, who); }
@@ -432,6 +485,30 @@ rac_status rac_steady_states(const rac_topology* topo, const rac_params_view* de
     std::vector<Job> jobs{{topo, *dev_params, dev_ic, n_ic, dev_x_out,
                            dev_info ? *dev_info : rac_traj_info{nullptr, nullptr, nullptr, nullptr}}};
     return run_jobs(jobs, opts, false, nullptr, 0, hip_stream);
+}
+
+rac_status rac_steady_states_noalloc(const rac_topology* topo, const rac_params_view* dev_params,
+                                     const float* dev_ic, int32_t n_ic, const rac_solver_opts* opts,
+                                     void* dev_x_out, const rac_traj_info* dev_info, void* hip_stream) {
+    using namespace rac;
+    rac_status st = check_opts(opts, "rac_steady_states_noalloc");
+    if (st != RAC_OK) return st;
+    if (!(opts->t_end > opts->t0)) return fail(RAC_EINVAL, "rac_steady_states_noalloc: t_end <= t0");
+    st = check_item(topo, dev_params, dev_ic, n_ic, dev_x_out, "rac_steady_states_noalloc");
+    if (st != RAC_OK) return st;
+    if (dev_params->n_sets == 0) return RAC_OK;
+    const int lpt = pick_lanes(topo, opts);
+    if (lpt == 0 || !plan_fits(topo, lpt, opts->precision))
+        return fail(RAC_EUNSUPPORTED, "rac_steady_states_noalloc: network does not fit the compiled kernels");
+    int dev = 0;
+    const hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess) return fail(RAC_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(he));
+    char* block = nullptr;
+    st = scratch_address(dev, &block);
+    if (st != RAC_OK) return st;
+    std::vector<Job> jobs{{topo, *dev_params, dev_ic, n_ic, dev_x_out,
+                           dev_info ? *dev_info : rac_traj_info{nullptr, nullptr, nullptr, nullptr}}};
+    return launch_group(jobs, lpt, opts, false, nullptr, 0, (hipStream_t)hip_stream, block);
 }
 
 rac_status rac_integrate(const rac_topology* topo, const rac_params_view* dev_params,

@@ -102,6 +102,9 @@ def lib():
         L.rac_steady_states.argtypes = [vp, C.POINTER(_ParamsView), vp, i32, C.POINTER(_Opts),
                                         vp, C.POINTER(_Info), vp]
         L.rac_steady_states.restype = C.c_int
+        L.rac_steady_states_noalloc.argtypes = [vp, C.POINTER(_ParamsView), vp, i32, C.POINTER(_Opts),
+                                                vp, C.POINTER(_Info), vp]
+        L.rac_steady_states_noalloc.restype = C.c_int
         L.rac_integrate.argtypes = [vp, C.POINTER(_ParamsView), vp, i32, C.POINTER(_Opts), vp,
                                     i32, vp, C.POINTER(_Info), vp]
         L.rac_integrate.restype = C.c_int
@@ -421,6 +424,20 @@ def steady_states(topo: Topology, params: DeviceParams, opts: Opts | None = None
     o = opts.c()
     _check(lib().rac_steady_states(topo.handle, C.byref(v), params.ic.data_ptr(), params.n_ic,
                                    C.byref(o), out.x.data_ptr(), C.byref(info), _stream_ptr(stream)))
+    return out
+
+
+def steady_states_noalloc(topo: Topology, params: DeviceParams, opts: Opts, out: Result,
+                          stream=None) -> Result:
+    """Enqueue rac_steady_states_noalloc: as steady_states into the caller's
+    `out`, with no device allocation (the network must have been solved once
+    with the same options on this device)."""
+    v = params.view()
+    info = _info(out)
+    o = opts.c()
+    _check(lib().rac_steady_states_noalloc(topo.handle, C.byref(v), params.ic.data_ptr(), params.n_ic,
+                                           C.byref(o), out.x.data_ptr(), C.byref(info),
+                                           _stream_ptr(stream)))
     return out
 
 

@@ -1,0 +1,62 @@
+"""The steady-state entry point without device allocation, through the C ABI,
+against rac_steady_states on the same inputs: bit-identical results on two
+calls in a row, the second with a smaller ensemble (the scratch keeps the
+first call's counter and descriptor, which the second must clear and
+replace)."""
+import numpy as np
+import pytest
+
+from paper_2503_18356_amd import inputs
+from paper_2503_18356_amd import racipe as rp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def _same(a, b):
+    for f in ("x", "t_final", "status", "n_acc", "n_rej"):
+        assert torch.equal(getattr(a, f), getattr(b, f)), f
+
+
+def _filled(n_traj, n_genes, precision):
+    # Sentinels: every output must be written by the call.
+    r = rp.alloc_result(n_traj, n_genes, precision)
+    r.x.fill_(float("nan"))
+    r.t_final.fill_(-1.0)
+    r.status.fill_(-1)
+    r.n_acc.fill_(-1)
+    r.n_rej.fill_(-1)
+    return r
+
+
+@pytest.mark.parametrize("prec", [rp.FP32, rp.FP64])
+def test_noalloc_matches_steady_states_twice(prec):
+    T = rp.Topology.from_inputs(inputs.erdos_renyi(10, 25, 1002))
+    opts = rp.Opts(precision=prec, ss_rtol=1e-5)
+    print(f"[gpu] noalloc prec={prec}", flush=True)
+    for n_sets, n_ic in ((3000, 20), (700, 3)):
+        dp = rp.sample_params(T, 321 + n_sets, n_sets, n_ic).to_device()
+        ref = rp.steady_states(T, dp, opts)
+        torch.cuda.synchronize()
+        out = _filled(n_sets * n_ic, T.n_genes, prec)
+        rp.steady_states_noalloc(T, dp, opts, out)
+        torch.cuda.synchronize()
+        _same(ref, out)
+        assert int((out.status < 0).sum()) == 0
+
+
+def test_noalloc_needs_a_prepared_lane_plan():
+    T = rp.Topology.from_inputs(inputs.dense_core(1004))
+    dp = rp.sample_params(T, 5, 10, 2).to_device()
+    out = _filled(20, T.n_genes, rp.FP32)
+    with pytest.raises(rp.RacError) as e:
+        rp.steady_states_noalloc(T, dp, rp.Opts(precision=rp.FP32), out)
+    assert e.value.code == rp.EINVAL
+    rp.steady_states(T, dp, rp.Opts(precision=rp.FP32))
+    torch.cuda.synchronize()
+    rp.steady_states_noalloc(T, dp, rp.Opts(precision=rp.FP32), out)
+    torch.cuda.synchronize()
+    assert int((out.status < 0).sum()) == 0
