@@ -17,7 +17,8 @@ HOST_SRC = ["topology.cpp", "sampler.cpp"]
 HIP_SRC = ["solver.hip", "sampler_device.hip", "kernels_f32_ss.hip", "kernels_f32_ts.hip", "kernels_f64_ss.hip",
            "kernels_f64_ts.hip", "kernels_f32_serve.hip", "server.hip", "kernels_f32_ss_tsit5.hip",
            "kernels_f32_ts_tsit5.hip", "kernels_f64_ss_tsit5.hip", "kernels_f64_ts_tsit5.hip",
-           "postproc.hip", "ising.hip", "ceilings.hip"]
+           "postproc.hip", "ising.hip", "ceilings.hip", "kernels_f64_realn.hip",
+           "kernels_f64_realn_tsit5.hip"]
 # Packed FP32 instructions are kept out of every HIP object.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=fast",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -94,8 +94,13 @@ struct Ops<float> {
     // with (b, d) = (sqrt(lam), 1/sqrt(lam) - sqrt(lam)) in the symmetric
     // form, or b = 1, d = D >= 0 and, for activation, n and n log2 T negated
     // in the base-free form (the kernel body picks the form per shape).
-    // x = 0 publishes -inf, giving the limit H^S = 1 in both forms.
-    __device__ static float publish(float v) { return __builtin_amdgcn_logf(v > 0.0f ? v : 0.0f); }
+    // x = 0 publishes -inf, giving the limit H^S = 1 in both forms.  The
+    // clamp at 0 is an integer max on the bits (a negative float is a
+    // negative int), one instruction instead of a canonicalised float max.
+    __device__ static float publish(float v) {
+        const int b = __builtin_bit_cast(int, v);
+        return __builtin_amdgcn_logf(__builtin_bit_cast(float, b > 0 ? b : 0));
+    }
     __device__ static float edge_t(float T, float n) { return n * __builtin_amdgcn_logf(T); }
     __device__ static float hill(float lx, float nlT, float n, float b, float d) {
         const float r = __builtin_amdgcn_exp2f(__builtin_fmaf(n, lx, -nlT));
@@ -104,10 +109,13 @@ struct Ops<float> {
     __device__ static float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
     __device__ static float abs(float v) { return __builtin_fabsf(v); }
     __device__ static float sqrt(float v) { return __builtin_sqrtf(v); }
-    // Step factor err^(-1/5) from the mean square err^2 (FP32 is ample for a
-    // controller factor).
-    __device__ static double pow_m15_sq(double err2) {
-        return (double)__builtin_amdgcn_exp2f(-0.1f * __builtin_amdgcn_logf((float)err2));
+    __device__ static float max(float a, float b) { return __builtin_fmaxf(a, b); }
+    // Step factor 0.9 err^(-1/5) from the mean square err^2 = err2 (finite),
+    // clamped to [0.2, fmax]; FP32 is ample for a controller factor (err2 = 0
+    // gives +inf, clamped to fmax).
+    __device__ static double step_factor(double err2, double fmax) {
+        const float f = 0.9f * __builtin_amdgcn_exp2f(-0.1f * __builtin_amdgcn_logf((float)err2));
+        return (double)__builtin_amdgcn_fmed3f(f, 0.2f, (float)fmax);
     }
     // v^(1/5) for the starting step (v > 0).
     __device__ static float root5(float v) { return __builtin_amdgcn_exp2f(0.2f * __builtin_amdgcn_logf(v)); }
@@ -116,35 +124,48 @@ struct Ops<float> {
 template <>
 struct Ops<double> {
     using NType = int;
-    // An integer Hill coefficient is kept as itself; a real one as its FP32
-    // bits with the sign bit set (a negative int: n > 0 always).
-    __device__ static int to_n(float n) {
-        return (n == __builtin_floorf(n) && n <= 64.0f) ? (int)n
-                                                        : (int)(__builtin_bit_cast(uint32_t, n) | 0x80000000u);
-    }
-    // Sources publish their level, edges keep 1/T; (x/T)^n by squaring, or
-    // exp(n log(x/T)) for a real n.
+    __device__ static int to_n(float n) { return (int)n; }
+    // Sources publish their level, edges keep 1/T; (x/T)^n by squaring.
     __device__ static double publish(double v) { return v > 0.0 ? v : 0.0; }
     __device__ static double edge_t(double T, float) { return 1.0 / T; }
     __device__ static double hill(double xs, double invT, int n, double b, double d) {
         const double q = xs * invT;
         double r = 1.0, base = q;
-        if (n >= 0) {
-            for (int e = n; e > 0; e >>= 1) {
-                if (e & 1) r *= base;
-                base *= base;
-            }
-        } else {
-            const float nf = __builtin_bit_cast(float, (uint32_t)n & 0x7fffffffu);
-            r = ::exp((double)nf * ::log(q));
+        for (int e = n; e > 0; e >>= 1) {
+            if (e & 1) r *= base;
+            base *= base;
         }
         return fma(d, 1.0 / (1.0 + r), b);
     }
     __device__ static double rcp(double v) { return 1.0 / v; }
     __device__ static double abs(double v) { return __builtin_fabs(v); }
     __device__ static double sqrt(double v) { return ::sqrt(v); }
-    __device__ static double pow_m15_sq(double err2) { return ::pow(err2, -0.1); }
+    __device__ static double max(double a, double b) { return a > b ? a : b; }
+    __device__ static double step_factor(double err2, double fmax) {
+        const double f = err2 > 0 ? 0.9 * ::pow(err2, -0.1) : 10.0;
+        return f < 0.2 ? 0.2 : (f > fmax ? fmax : f);
+    }
     __device__ static double root5(double v) { return ::pow(v, 0.2); }
+};
+
+// FP64 kernels for real Hill coefficients (the nf array): (x/T)^n as
+// exp(n log(x/T)).  A separate instantiation, so that the integer kernels
+// carry no exp/log code and no extra registers.
+struct OpsRealN : Ops<double> {
+    using NType = float;
+    __device__ static float to_n(float n) { return n; }
+    __device__ static double hill(double xs, double invT, float n, double b, double d) {
+        const double r = ::exp((double)n * ::log(xs * invT));
+        return fma(d, 1.0 / (1.0 + r), b);
+    }
+};
+template <typename R, bool REALN>
+struct OpsFor {
+    using type = Ops<R>;
+};
+template <>
+struct OpsFor<double, true> {
+    using type = OpsRealN;
 };
 
 // Wave-level ordering of LDS writes before reads by other lanes of the wave.
@@ -220,7 +241,9 @@ constexpr int kLongSteps = 100;
 //                               q * 64 + lane (private to the lane: loaded with
 //                               the trajectory, read by every right-hand side)
 //   then 16 bytes per lane      the group's network record (1/N, N, network
-//                               index), private to the lane, read once a step
+//   (32 in time-series mode)    index; in time-series mode also the address
+//                               of the trajectory's output rows), private to
+//                               the lane, read once a step
 // Every address a lane uses is precomputed as an absolute LDS byte offset.
 // The level stride S = 96 / lpt spreads the sources that the lanes of a half
 // wave read in one edge slot over the 32 LDS banks: group g's copies of one
@@ -228,16 +251,24 @@ constexpr int kLongSteps = 100;
 // start at banks 24, 16 or 8 apart (S = 24 at 4 lanes; the levels written by
 // one half wave fall on 32 distinct banks).
 constexpr int kPubStride = 96;
-template <typename R, int EPL, int GPL>
-struct LdsLayout {
-    static constexpr int kPub = kPubStride * GPL;
-    static constexpr int kRec = kPub + 64 * (EPL + 2 + 2 * GPL);  // start of the network records
-    static constexpr int kWaveElems = kRec + 64 * 16 / (int)sizeof(R);
-};
-
+template <bool TS>
 struct alignas(16) GroupRec {
     double inv_n;  // 1 / N of the group's network
     int32_t n_genes, net;
+};
+template <>
+struct alignas(16) GroupRec<true> {
+    double inv_n;
+    int32_t n_genes, net;
+    void* xo;      // first output row of the group's trajectory
+    int64_t pad;
+};
+
+template <typename R, int EPL, int GPL, bool TS>
+struct LdsLayout {
+    static constexpr int kPub = kPubStride * GPL;
+    static constexpr int kRec = kPub + 64 * (EPL + 2 + 2 * GPL);  // start of the network records
+    static constexpr int kWaveElems = kRec + 64 * (int)sizeof(GroupRec<TS>) / (int)sizeof(R);
 };
 
 template <typename R>
@@ -276,13 +307,15 @@ constexpr int requested_waves() {
     return (EPL == 12 && GPL == 8) ? 2 : 1;
 }
 
-template <typename R, int EPL, int GPL, bool TS, bool BOUNDED = false, int M = kDP5>
+template <typename R, int EPL, int GPL, bool TS, bool BOUNDED = false, int M = kDP5, bool REALN = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(requested_waves<R, EPL, GPL, TS, BOUNDED, M>(), 8)))
 void dp5_kernel(LaunchArgs a) {
     static_assert(!(TS && BOUNDED), "serving step batches run in steady-state mode");
-    using O = Ops<R>;
+    static_assert(!REALN || sizeof(R) == 8, "FP32 kernels take real coefficients natively");
+    using O = typename OpsFor<R, REALN>::type;
     using NT = typename O::NType;
-    using Lay = LdsLayout<R, EPL, GPL>;
+    using Lay = LdsLayout<R, EPL, GPL, TS>;
+    using Rec = GroupRec<TS>;
     static_assert(EPL >= 1, "at least one edge slot");
     __shared__ R lds[(kBlock / 64) * Lay::kWaveElems];
     char* const lb = reinterpret_cast<char*>(lds);
@@ -367,8 +400,10 @@ void dp5_kernel(LaunchArgs a) {
     // Indices this wave has claimed but not started: [claim_next, claim_end).
     uint64_t claim_next = 0, claim_end = 0;
     // The group's network (index, N, 1/N), kept in LDS rather than registers.
-    GroupRec* const rec = reinterpret_cast<GroupRec*>(lb + (wave_elem + Lay::kRec) * SZ + 16 * lane);
-    *rec = GroupRec{1.0, 1, 0};
+    Rec* const rec = reinterpret_cast<Rec*>(lb + (wave_elem + Lay::kRec) * SZ + sizeof(Rec) * lane);
+    rec->inv_n = 1.0;
+    rec->n_genes = 1;
+    rec->net = 0;
     // Gene slot q of this lane holds gene r + q * lpt; slots past N pad.
     auto gene_of = [&](int q) { return r + q * lpt; };
     auto is_real = [&](int q) { return r + q * lpt < rec->n_genes; };
@@ -417,17 +452,18 @@ void dp5_kernel(LaunchArgs a) {
         const NetDesc* dp = a.nets + rec->net;
         const int N = dp->n_genes;
         const int64_t local = traj - dp->traj_begin;
-        R* const xo = (R*)dp->x_out + local * (int64_t)(TS ? a.n_t : 1) * N;
-        if (!TS) {
+        if constexpr (!TS) {
+            R* const xo = (R*)dp->x_out + local * N;
 #pragma unroll
             for (int q = 0; q < GPL; ++q)
                 if (is_real(q)) xo[gene_of(q)] = x[q];
         } else {
             // Steady before the last output: the remaining outputs hold x_ss.
+            R* const xo = (R*)rec->xo;
             for (int k = kout; k < a.n_t; ++k)
 #pragma unroll
                 for (int q = 0; q < GPL; ++q)
-                    if (is_real(q)) xo[(int64_t)k * N + gene_of(q)] = x[q];
+                    if (is_real(q)) xo[k * N + gene_of(q)] = x[q];
         }
         if (r == 0) {
             double* tf = dp->t_final;
@@ -481,7 +517,10 @@ void dp5_kernel(LaunchArgs a) {
             const int ci = (int)(local - p * n_ic);
             const int64_t P = dp->n_sets;
             const int n_genes = dp->n_genes;
-            *rec = GroupRec{1.0 / n_genes, n_genes, net};
+            rec->inv_n = 1.0 / n_genes;
+            rec->n_genes = n_genes;
+            rec->net = net;
+            if constexpr (TS) rec->xo = (R*)dp->x_out + local * (int64_t)a.n_t * n_genes;
             const int stride = dp->stride;
             const int32_t* lane_edge = dp->lane_edge + r * stride;
             const float* Tp = dp->T + p;
@@ -719,16 +758,15 @@ void dp5_kernel(LaunchArgs a) {
             const bool all_steady = group_all(steady);
             const int n_genes = rec->n_genes;
             const R d0 = O::sqrt(group_sumr(s0) / (R)n_genes), d1 = O::sqrt(group_sumr(s1) / (R)n_genes);
-            if (TS && fresh) {
-                const NetDesc* dp = a.nets + rec->net;
-                const int N = dp->n_genes;
-                const int64_t local = traj - (dp->traj_begin);
-                R* xo = (R*)(dp->x_out) + local * (int64_t)a.n_t * N;
-                while (kout < a.n_t && a.t_out[kout] <= t) {
+            if constexpr (TS) {
+                if (fresh) {
+                    R* const xo = (R*)rec->xo;
+                    while (kout < a.n_t && a.t_out[kout] <= t) {
 #pragma unroll
-                    for (int q = 0; q < GPL; ++q)
-                        if (is_real(q)) xo[(int64_t)kout * N + gene_of(q)] = x[q];
-                    ++kout;
+                        for (int q = 0; q < GPL; ++q)
+                            if (is_real(q)) xo[kout * n_genes + gene_of(q)] = x[q];
+                        ++kout;
+                    }
                 }
             }
             const R hmax = (R)(t_stop - c.t0);
@@ -824,8 +862,7 @@ void dp5_kernel(LaunchArgs a) {
             if (tab_e<M>(6) != 0.0) e += (R)tab_e<M>(6) * kk[6][q];
             // Scaled error e_i / (atol + rtol max(|x_i|, |x_new,i|)); the ratio
             // in R, its square accumulated in FP64.
-            const R ax = O::abs(x[q]), an = O::abs(y[q]);
-            const R sc = (R)c.atol + (R)c.rtol * (ax > an ? ax : an);
+            const R sc = (R)c.atol + (R)c.rtol * O::max(O::abs(x[q]), O::abs(y[q]));
             const double rq = (double)(hR * e * O::rcp(sc));
             serr += rq * rq;
             fin = fin && __builtin_isfinite(y[q]);
@@ -836,24 +873,21 @@ void dp5_kernel(LaunchArgs a) {
         const double err2 = group_sum(serr) * rec->inv_n;
         const bool all_fin = group_all(fin);  // collective: evaluated by every lane
         const bool accept = running && all_fin && err2 <= 1.0;
-        const bool err_ok = __builtin_isfinite(err2);
-        double fac = !err_ok ? 0.2 : (err2 > 0 ? 0.9 * O::pow_m15_sq(err2) : 10.0);
         const double fmax = (accept && !last_rej) ? 10.0 : 1.0;
-        fac = fac < 0.2 ? 0.2 : (fac > fmax ? fmax : fac);
+        const double fac = __builtin_isfinite(err2) ? O::step_factor(err2, fmax) : 0.2;
         if (running) {
             h = hs * fac;
             nrej += accept ? 0 : 1;
             last_rej = !accept;
         }
         // Dense output for every output time inside the accepted step.
-        if (TS && accept && kout < a.n_t && a.t_out[kout] <= (clipped ? t_stop : t + hs)) {
-            const NetDesc* dp = a.nets + rec->net;
-            const int N = dp->n_genes;
-            const int64_t local = traj - (dp->traj_begin);
-            R* xo = (R*)(dp->x_out) + local * (int64_t)a.n_t * N;
+        if constexpr (TS) if (accept && kout < a.n_t && a.t_out[kout] <= (clipped ? t_stop : t + hs)) {
+            R* const xo = (R*)rec->xo;
+            const int N = rec->n_genes;
             const double t_new = clipped ? t_stop : t + hs;
+            const R ih = O::rcp(hR);  // theta in the state precision
             while (kout < a.n_t && a.t_out[kout] <= t_new) {
-                const R th = (R)((a.t_out[kout] - t) / hs);
+                const R th = (R)(a.t_out[kout] - t) * ih;
                 if constexpr (M == kTsit5) {
                     R bt[7];
 #pragma unroll
@@ -866,7 +900,7 @@ void dp5_kernel(LaunchArgs a) {
                             R acc = bt[0] * kk[0][q];
 #pragma unroll
                             for (int l = 1; l < 7; ++l) acc += bt[l] * kk[l][q];
-                            xo[(int64_t)kout * N + gene_of(q)] = x[q] + hR * acc;
+                            xo[kout * N + gene_of(q)] = x[q] + hR * acc;
                         }
                     }
                 } else {
@@ -883,7 +917,7 @@ void dp5_kernel(LaunchArgs a) {
 #pragma unroll
                             for (int l = 2; l < 7; ++l) c5 += (R)kDense[l] * kk[l][q];
                             c5 *= hR;
-                            xo[(int64_t)kout * N + gene_of(q)] =
+                            xo[kout * N + gene_of(q)] =
                                 x[q] + th * (ydiff + th1 * (bspl + th * (c4 + th1 * c5)));
                         }
                     }
@@ -891,7 +925,6 @@ void dp5_kernel(LaunchArgs a) {
                 ++kout;
             }
         }
-        bool steady = true;
         if (accept) {
             ++nacc;
             t = clipped ? t_stop : t + hs;
@@ -899,12 +932,19 @@ void dp5_kernel(LaunchArgs a) {
             for (int q = 0; q < GPL; ++q) {
                 x[q] = y[q];
                 kk[0][q] = kk[6][q];
-                steady = steady && is_steady(kk[0][q], rate(q).k, x[q]);
             }
         }
-        const bool all_steady = group_all(steady);
+        // Steady test after an accepted step (uniform branch: time series stop
+        // only with stop_at_steady).
+        bool all_steady = false;
+        if (!TS || c.stop_at_steady) {
+            bool steady = accept;
+#pragma unroll
+            for (int q = 0; q < GPL; ++q) steady = steady && is_steady(kk[0][q], rate(q).k, x[q]);
+            all_steady = group_all(steady);
+        }
         if (accept) {
-            if ((!TS || c.stop_at_steady) && all_steady) finish(RAC_CONVERGED);
+            if (all_steady) finish(RAC_CONVERGED);
             else if (t >= t_stop) finish(RAC_T_END);
         }
     }

@@ -14,6 +14,7 @@ struct KernelEntry {
     bool bounded;   // serving step-batch variant
     const void* fn; // __global__ function
     int method;     // RAC_DP5 / RAC_TSIT5
+    bool realn = false;  // FP64 kernel for real Hill coefficients
 };
 
 // Each instantiation unit appends its entries.
@@ -26,8 +27,10 @@ int kernels_f32_ss_tsit5(const KernelEntry** out);
 int kernels_f32_ts_tsit5(const KernelEntry** out);
 int kernels_f64_ss_tsit5(const KernelEntry** out);
 int kernels_f64_ts_tsit5(const KernelEntry** out);
+int kernels_f64_realn(const KernelEntry** out);
+int kernels_f64_realn_tsit5(const KernelEntry** out);
 
 const KernelEntry* find_kernel(int precision, bool ts, int epl, int gpl, bool bounded = false,
-                               int method = RAC_DP5);
+                               int method = RAC_DP5, bool realn = false);
 
 }  // namespace rac

@@ -22,12 +22,12 @@ namespace rac {
             return fail(RAC_EDEVICE, std::string(what) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-const KernelEntry* find_kernel(int precision, bool ts, int epl, int gpl, bool bounded, int method) {
+const KernelEntry* find_kernel(int precision, bool ts, int epl, int gpl, bool bounded, int method, bool realn) {
     static std::vector<KernelEntry> all = [] {
         std::vector<KernelEntry> v;
         for (auto fn : {kernels_f32_ss, kernels_f32_ts, kernels_f64_ss, kernels_f64_ts, kernels_f32_serve,
                         kernels_f32_ss_tsit5, kernels_f32_ts_tsit5, kernels_f64_ss_tsit5,
-                        kernels_f64_ts_tsit5}) {
+                        kernels_f64_ts_tsit5, kernels_f64_realn, kernels_f64_realn_tsit5}) {
             const KernelEntry* t = nullptr;
             int n = fn(&t);
             v.insert(v.end(), t, t + n);
@@ -36,7 +36,7 @@ const KernelEntry* find_kernel(int precision, bool ts, int epl, int gpl, bool bo
     }();
     for (const KernelEntry& k : all)
         if (k.precision == precision && k.ts == ts && k.epl == epl && k.gpl == gpl && k.bounded == bounded &&
-            k.method == method)
+            k.method == method && k.realn == realn)
             return &k;
     return nullptr;
 }
@@ -283,8 +283,14 @@ rac_status launch_group(const std::vector<Job>& jobs, int lpt, const rac_solver_
     }
     if (total == 0) return RAC_OK;
     const Shape shape = pick_shape(std::max(epl, 1), gpl, o->precision);
+    // FP64 launches with real Hill coefficients in any network take the
+    // exp/log kernels (integer coefficients of the other networks are read as
+    // floats there); FP32 kernels handle both.
+    bool realn = false;
+    for (const NetDesc& d : descs) realn = realn || d.nf != nullptr;
+    realn = realn && o->precision == RAC_FP64;
     const KernelEntry* ke =
-        shape.epl ? find_kernel(o->precision, ts, shape.epl, shape.gpl, false, o->method) : nullptr;
+        shape.epl ? find_kernel(o->precision, ts, shape.epl, shape.gpl, false, o->method, realn) : nullptr;
     if (!ke) return fail(RAC_EUNSUPPORTED, "no compiled kernel for this network size and lane count");
 
     int dev = 0, n_cu = 0;
@@ -521,6 +527,8 @@ rac_status rac_integrate(const rac_topology* topo, const rac_params_view* dev_pa
     st = check_item(topo, dev_params, dev_ic, n_ic, dev_x_out, "rac_integrate");
     if (st != RAC_OK) return st;
     if (n_t < 1 || !host_t_out) return fail(RAC_EINVAL, "rac_integrate: need n_t >= 1 output times");
+    if ((int64_t)n_t * topo->n_genes >= ((int64_t)1 << 31))
+        return fail(RAC_EUNSUPPORTED, "rac_integrate: n_t x N must stay below 2^31 (one trajectory's series)");
     for (int i = 0; i < n_t; ++i) {
         if (!std::isfinite(host_t_out[i]) || host_t_out[i] < opts->t0)
             return fail(RAC_EINVAL, "rac_integrate: output time before t0 or not finite");
