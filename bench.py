@@ -1,22 +1,26 @@
 """RACIPE ensemble benchmark on one MI355X.
 
-Default workload (one "step"): steady states of every trajectory of a seeded
-random 10-gene / 25-edge signed network (Erdos-Renyi, half inhibitory, no
-isolated node), 10,000 parameter sets x 100 initial conditions = 10^6
-trajectories, Table 1 parameter ranges (GRiNS Sec. 2.1.2), DP5(4) with rtol
-1e-6, atol 1e-9, t_end 200, steady when |dx_i/dt| <= 1e-6 + 1e-5 k_i |x_i|.
-Parameters and initial conditions are resident in HBM before timing starts.
+Default workload (one "step"): steady states of every trajectory of an uneven
+batch of 64 seeded random signed networks (N ~ U{5..50} genes, E = 2.5N edges,
+half inhibitory, Erdos-Renyi without isolated genes), each with a
+log-uniform 2,000-50,000 parameter sets x 10 initial conditions (about 10^7
+trajectories in all), Table 1 parameter ranges (GRiNS Sec. 2.1.2), DP5(4)
+with rtol 1e-6, atol 1e-9, t_end 200, steady when |dx_i/dt| <= 1e-6 +
+1e-5 k_i |x_i|.  Parameters and initial conditions are resident in HBM before
+timing starts.  The chosen form is FP32 state with FP64 time / error norm /
+steady test in persistent work-queue launches with lane counts from the
+autotuner; the plain form is FP64, one launch per network.
 
-The JSON line reports solves/s of the chosen form (FP32 state, FP64 time /
-error norm / steady test, persistent work-queue kernel), the plain FP64 form
-on the same workload, the kernel's credited FP32 FLOP/s against the MI355X
-vector peak, p50/p99 request latency of a short Poisson serving run, and the
-CPU oracle timed on a bounded sample on this host.
+The JSON line reports solves/s of the chosen form, the plain form, the
+credited FP32 FLOP/s of the batch call against the MI355X vector peak, the
+CPU oracle timed on a bounded sample on this host, parity against the oracle
+on 1 % of every network, and, under "extras", the other configurations: the
+10-gene network (10^6 trajectories), the 22-gene series (10^6 trajectories x
+101 outputs), the toggle switch and the Poisson serving stream (2,000
+requests after 200 warm-up at 200 req/s, p50/p99 latency).
 
-Other workloads (--workload): ts (2-gene toggle switch, 1000 x 10, FP64 plain
-vs FP32), uneven64 (64 networks of 5-50 genes fused in persistent launches),
-core22ts (22-gene / 82-edge network, 10^5 x 10, 101 outputs on [0, 100]),
-serve (Poisson stream, 200 req/s, 2,000 requests after 200 warm-up).
+Single workloads (--workload): er10, ts, uneven64 (without extras: --no-extras),
+core22ts, serve, ising.
 """
 from __future__ import annotations
 
@@ -64,14 +68,18 @@ def measured_traffic(workload: str):
     return None
 
 
-def timed(fn, steps, stream, torch):
+def timed(fn, steps, stream, torch, before_last=None):
     """Run fn() `steps` times between synchronisations; HIP events on the
-    launch stream bracket each call."""
+    launch stream bracket each call.  before_last() runs ahead of the last
+    call, outside its event pair (it marks the outputs with sentinels, so
+    that the statuses counted afterwards are the last call's own)."""
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(steps)]
     torch.cuda.synchronize()
     w0 = time.perf_counter()
-    for e0, e1 in evs:
+    for i, (e0, e1) in enumerate(evs):
+        if before_last is not None and i == steps - 1:
+            before_last()
         e0.record(stream)
         fn()
         e1.record(stream)
@@ -80,8 +88,13 @@ def timed(fn, steps, stream, torch):
     return wall, np.array([e0.elapsed_time(e1) for e0, e1 in evs])
 
 
-def solved(rp, status) -> int:
-    st = status.cpu().numpy()
+def solved(rp, out) -> int:
+    """Trajectories of `out` that ended CONVERGED or T_END; fails if any
+    output still holds the sentinel of fill_sentinels (a dropped trajectory)."""
+    left = rp.unfinished(out)
+    if left:
+        raise RuntimeError(f"{left} trajectories were never written")
+    st = out.status.cpu().numpy()
     return int(np.isin(st, (rp.CONVERGED, rp.T_END)).sum())
 
 
@@ -239,12 +252,6 @@ def base_record(args):
 
 def bench_er10(args, torch, rp, flops, inputs):
     dev = torch.device("cuda:0")
-    if args.calibrate_copy:
-        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     topo = inputs.erdos_renyi(10, 25, seed=1002, inhib_frac=0.5)
     T = rp.Topology.from_inputs(topo)
     t0 = time.time()
@@ -258,11 +265,11 @@ def bench_er10(args, torch, rp, flops, inputs):
     step = lambda: rp.steady_states(T, dp, opts, out=out, stream=stream)
     for _ in range(args.warmup):
         step()
-    wall, lat = timed(step, args.steps, stream, torch)
+    wall, lat = timed(step, args.steps, stream, torch, before_last=lambda: rp.fill_sentinels(out))
+    value = solved(rp, out) * args.steps / wall
     nacc = out.n_acc.cpu().numpy().astype(np.int64)
     nrej = out.n_rej.cpu().numpy().astype(np.int64)
     x_er10 = out.x.cpu().numpy()
-    value = solved(rp, out.status) * args.steps / wall
     achieved = flops.credited(T.n_genes, hp.n, args.n_ic, nacc + nrej) / (lat.mean() * 1e-3)
     nbytes = flops.algorithmic_bytes(T.n_genes, T.n_edges, args.n_sets, args.n_ic, 4)
     default_cfg = (args.n_sets, args.n_ic, args.lanes, args.refill_min) == (10000, 100, 0, 0)
@@ -310,8 +317,8 @@ def bench_er10(args, torch, rp, flops, inputs):
         out64 = rp.alloc_result(n_traj, T.n_genes, rp.FP64, device=dev)
         s64 = lambda: rp.steady_states(T, dp, o64, out=out64, stream=stream)
         s64()
-        w64, _ = timed(s64, 1, stream, torch)
-        v64 = solved(rp, out64.status) / w64
+        w64, _ = timed(s64, 1, stream, torch, before_last=lambda: rp.fill_sentinels(out64))
+        v64 = solved(rp, out64) / w64
         steps64 = out64.n_acc.cpu().numpy().astype(np.int64) + out64.n_rej.cpu().numpy()
         fl64 = flops.credited(T.n_genes, hp.n, args.n_ic, steps64) / w64
         rec["plain_fp64"] = {"value": v64, "unit": "solves/s", "ms_per_step": w64 * 1e3,
@@ -343,20 +350,16 @@ def bench_er10(args, torch, rp, flops, inputs):
                        refill_min=args.refill_min)
         step_ts = lambda: rp.steady_states(T, dp, o_ts, out=out, stream=stream)
         step_ts()
-        w_ts, lat_ts = timed(step_ts, max(1, args.steps), stream, torch)
+        w_ts, lat_ts = timed(step_ts, max(1, args.steps), stream, torch, before_last=lambda: rp.fill_sentinels(out))
         rec["tsit5_fp32"] = {
-            "value": solved(rp, out.status) * max(1, args.steps) / w_ts, "unit": "solves/s",
+            "value": solved(rp, out) * max(1, args.steps) / w_ts, "unit": "solves/s",
             "kernel_ms": float(lat_ts.mean()),
             "steps_per_solve": float((out.n_acc.cpu().numpy().astype(np.int64)
                                       + out.n_rej.cpu().numpy()).mean()),
             "what": "FP32 chosen form with the Tsitouras 5(4) pair instead of Dormand-Prince"}
-    if not args.no_serve:
-        rec["serving"] = serving_run(args.serve_requests, args.serve_warmup, args.serve_rate)
-        rec["latency_ms"] = {"p50": rec["serving"]["p50_ms"], "p99": rec["serving"]["p99_ms"],
-                             "what": "serving request latency at the stated offered rate"}
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_oracle(topo, 2002, args.n_sets, args.n_ic, args.cpu_sample or 20000,
-                                          gpu_steps=nacc + nrej)
+                                          gpu_steps=nacc + nrej, target_s=args.cpu_seconds)
         ids = np.sort(np.random.default_rng(1).choice(n_traj, min(n_traj, 10000), replace=False))
         rec["parity"] = parity_report(topo, 2002, args.n_sets, args.n_ic, ids, x_er10[ids],
                                       {"ss_rtol": 1e-5})
@@ -374,8 +377,8 @@ def bench_ts(args, torch, rp, flops, inputs):
         out = rp.alloc_result(10000, 2, o.precision)
         fn = lambda: rp.steady_states(T, dp, o, out=out, stream=stream)
         fn()
-        wall, lat = timed(fn, args.steps, stream, torch)
-        res[name] = {"solves_per_s": solved(rp, out.status) * args.steps / wall,
+        wall, lat = timed(fn, args.steps, stream, torch, before_last=lambda: rp.fill_sentinels(out))
+        res[name] = {"solves_per_s": solved(rp, out) * args.steps / wall,
                      "kernel_ms": float(lat.mean())}
         x_last = out.x.cpu().numpy()
     rec = base_record(args)
@@ -385,70 +388,114 @@ def bench_ts(args, torch, rp, flops, inputs):
                                        "FP64 plain (steady |f| < 1e-6) and FP32"},
                 "forms": res})
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_oracle(topo, 2001, 1000, 10, 2000, {"ss_rtol": 0.0})
+        rec["cpu_baseline"] = cpu_oracle(topo, 2001, 1000, 10, 2000, {"ss_rtol": 0.0}, target_s=args.cpu_seconds)
         # The whole ensemble, FP32 form (the last one run) against the oracle
         # with the FP32 steady criterion.
         rec["parity"] = parity_report(topo, 2001, 1000, 10, np.arange(10000), x_last, {"ss_rtol": 1e-5})
     return rec
 
 
-def bench_uneven64(args, torch, rp, flops, inputs):
+def uneven64_inputs(rp, inputs):
+    """The 64-network uneven batch: topologies, parameter-set counts, seeds."""
     rng = np.random.default_rng(1003)
     topos = inputs.uneven_batch(1003, n_networks=64, n_min=5, n_max=50)
-    Ts = [rp.Topology.from_inputs(t) for t in topos]
     Ps = [inputs.log_uniform_int(rng, 2000, 50000) for _ in topos]
+    return topos, Ps
+
+
+def bench_uneven64(args, torch, rp, flops, inputs):
+    topos, Ps = uneven64_inputs(rp, inputs)
+    Ts = [rp.Topology.from_inputs(t) for t in topos]
+    t0 = time.time()
     items = []
     for i, (T, P) in enumerate(zip(Ts, Ps)):
-        items.append((T, rp.sample_params(T, 3000 + i, P, 10).to_device()))
+        items.append((T, rp.sample_params_device(T, 3000 + i, P, 10)))
+    torch.cuda.synchronize()
+    t_sample = time.time() - t0
     n_traj = sum(P * 10 for P in Ps)
     stream = torch.cuda.current_stream()
     o32 = rp.Opts(precision=rp.FP32)
     outs = [rp.alloc_result(p.n_sets * 10, T.n_genes, rp.FP32) for T, p in items]
+    fill = lambda: [rp.fill_sentinels(o) for o in outs]
     fn = lambda: rp.steady_states_batch([(T, p, o) for (T, p), o in zip(items, outs)], o32, stream=stream)
-    fn()
-    wall, lat = timed(fn, args.steps, stream, torch)
-    v32 = sum(solved(rp, o.status) for o in outs) * args.steps / wall
-    fl = sum(flops.credited(T.n_genes, p.n.cpu().numpy(), 10,
-                            (o.n_acc.cpu().numpy().astype(np.int64) + o.n_rej.cpu().numpy()))
-             for (T, p), o in zip(items, outs))
-    o64 = rp.Opts(precision=rp.FP64, ss_rtol=1e-5)
-    outs64 = [rp.alloc_result(p.n_sets * 10, T.n_genes, rp.FP64) for T, p in items]
-
-    def plain():
-        for (T, p), o in zip(items, outs64):
-            rp.steady_states(T, p, o64, out=o, stream=stream)
-    plain()
-    w64, _ = timed(plain, 1, stream, torch)
-    v64 = sum(solved(rp, o.status) for o in outs64) / w64
+    for _ in range(max(1, args.warmup)):
+        fn()
+    wall, lat = timed(fn, args.steps, stream, torch, before_last=fill)
+    v32 = sum(solved(rp, o) for o in outs) * args.steps / wall
+    steps_all = [o.n_acc.cpu().numpy().astype(np.int64) + o.n_rej.cpu().numpy() for o in outs]
+    ns = [p.n.cpu().numpy() for _, p in items]
+    fl = sum(flops.credited(T.n_genes, n, 10, st) for (T, _), n, st in zip(items, ns, steps_all))
+    launch_ms = float(lat.mean())
+    achieved = fl / (launch_ms * 1e-3)
+    nbytes = sum(flops.algorithmic_bytes(T.n_genes, T.n_edges, p.n_sets, 10, 4) for T, p in items)
+    st_all = np.concatenate([o.status.cpu().numpy() for o in outs])
+    default_cfg = args.lanes == 0 and args.refill_min == 0
     rec = base_record(args)
-    rec.update({"value": v32, "unit": "solves/s", "ms_per_step": wall / args.steps * 1e3,
-                "config": {"workload": "64 random signed networks, N ~ U{5..50}, E = 2.5N, half "
-                                       "inhibitory, P log-uniform 2000-50000 x 10 ICs, one "
-                                       "persistent launch per kernel shape",
-                           "trajectories": n_traj},
-                "roofline": {"bound": "alu", "achieved": fl / (lat.mean() * 1e-3) / 1e12,
-                             "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                             "frac": fl / (lat.mean() * 1e-3) / PEAK_FP32,
-                             "frac_of_unpacked_fma_peak": fl / (lat.mean() * 1e-3) / PEAK_FP32_UNPACKED,
-                             "traffic": None},
-                "plain_fp64": {"value": v64, "unit": "solves/s",
-                               "what": "FP64, one launch per network"},
-                "speedup_fp32_vs_fp64": v32 / v64})
+    rec.update({
+        "value": v32, "unit": "solves/s", "ms_per_step": wall / args.steps * 1e3,
+        "config": {"workload": "steady states of an uneven batch of 64 seeded random signed networks "
+                               "(N ~ U{5..50}, E = 2.5N, half inhibitory, ER without isolated genes), "
+                               "P log-uniform in [2000, 50000] parameter sets x 10 initial conditions "
+                               "each, Table 1 ranges, DP5(4) rtol 1e-6 atol 1e-9 t_end 200, FP32 state "
+                               "with FP64 t / error norm / steady test",
+                   "trajectories": n_traj, "networks": len(items),
+                   "genes": [T.n_genes for T in Ts]},
+        "roofline": {
+            "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32, "frac_of_unpacked_fma_peak": achieved / PEAK_FP32_UNPACKED,
+            "traffic": measured_traffic("uneven64_fp32") if default_cfg else None,
+            "traffic_unit": "bytes per batch call (rocprofv3 FETCH_SIZE + WRITE_SIZE over its launches, "
+                            "copy-calibrated)",
+            "algorithmic_bytes_per_launch": nbytes,
+            "hbm_frac": nbytes / (launch_ms * 1e-3) / PEAK_HBM,
+            "what": "credited FLOP of the whole batch call (all its persistent launches, overlapped on "
+                    "four streams) over the call's duration between HIP events on the caller's stream, "
+                    "which the call forks from and joins"},
+        "kernel_ms": {"mean": launch_ms, "p50": float(np.percentile(lat, 50)),
+                      "p99": float(np.percentile(lat, 99))},
+        "status_counts": {rp.STATUS_NAMES[i]: int(c) for i, c in enumerate(np.bincount(st_all, minlength=5))},
+        "steps_per_solve": float(np.concatenate(steps_all).mean()),
+        "device_sampling_s": t_sample,
+    })
+    if not args.no_plain:
+        o64 = rp.Opts(precision=rp.FP64, ss_rtol=1e-5)
+        outs64 = [rp.alloc_result(p.n_sets * 10, T.n_genes, rp.FP64) for T, p in items]
+
+        def plain():
+            for (T, p), o in zip(items, outs64):
+                rp.steady_states(T, p, o64, out=o, stream=stream)
+        plain()
+        w64, l64 = timed(plain, 1, stream, torch, before_last=lambda: [rp.fill_sentinels(o) for o in outs64])
+        v64 = sum(solved(rp, o) for o in outs64) / w64
+        fl64 = sum(flops.credited(T.n_genes, n, 10, o.n_acc.cpu().numpy().astype(np.int64) + o.n_rej.cpu().numpy())
+                   for (T, _), n, o in zip(items, ns, outs64))
+        rec["plain_fp64"] = {"value": v64, "unit": "solves/s", "ms": float(l64.mean()),
+                             "credited_fp64_tflops": fl64 / (l64.mean() * 1e-3) / 1e12,
+                             "frac_of_fp64_peak": fl64 / (l64.mean() * 1e-3) / PEAK_FP64,
+                             "what": "FP64 state and RHS, one launch per network in sequence on one stream, "
+                                     "same steady criterion"}
+        rec["speedup_fp32_vs_fp64"] = v32 / v64
+        del outs64
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_oracle_multi(
-            [(t, 3000 + i, P, 10) for i, (t, P) in enumerate(zip(topos, Ps))], 4000)
-        # 200 seeded trajectories of every network.
+            [(t, 3000 + i, P, 10) for i, (t, P) in enumerate(zip(topos, Ps))], 4000, target_s=args.cpu_seconds)
+        # 1 % of every network (at least 200 trajectories), seeded.
         reps = []
         prng = np.random.default_rng(2)
+        worst = 0.0
         for i, (t, P, o) in enumerate(zip(topos, Ps, outs)):
-            ids = np.sort(prng.choice(P * 10, 200, replace=False))
-            reps.append(parity_report(t, 3000 + i, P, 10, ids, o.x.cpu().numpy()[ids], {"ss_rtol": 1e-5}))
+            ids = np.sort(prng.choice(P * 10, max(200, P * 10 // 100), replace=False))
+            idt = torch.from_numpy(ids).to(o.x.device)
+            rep = parity_report(t, 3000 + i, P, 10, ids, o.x[idt].cpu().numpy(), {"ss_rtol": 1e-5})
+            reps.append(rep)
         rec["parity"] = {"n": sum(r["n"] for r in reps),
                          "max_norm_err": max(r["max_norm_err"] for r in reps),
+                         "p99_norm_err": max(r["p99_norm_err"] for r in reps),
                          "trajectories_over_1e-4": sum(r["trajectories_over_1e-4"] for r in reps),
                          "networks": len(reps),
-                         "what": "GPU FP32 vs the FP64 oracle, 200 seeded trajectories per network; "
-                                 "error = |x_gpu - x_ref| / (G/k) per component"}
+                         "what": "GPU FP32 vs the FP64 oracle on 1 % of every network (at least 200), "
+                                 "seeded; error = |x_gpu - x_ref| / (G/k) per component; p99 is the "
+                                 "worst network's"}
     return rec
 
 
@@ -464,10 +511,10 @@ def bench_core22ts(args, torch, rp, flops, inputs):
     out = rp.alloc_result(P * n_ic, T.n_genes, rp.FP32, n_t=101)
     fn = lambda: rp.integrate(T, dp, tk, o32, out=out, stream=stream)
     fn()
-    wall, lat = timed(fn, args.steps, stream, torch)
+    wall, lat = timed(fn, args.steps, stream, torch, before_last=lambda: rp.fill_sentinels(out))
+    v32 = solved(rp, out) * args.steps / wall
     steps = out.n_acc.cpu().numpy().astype(np.int64) + out.n_rej.cpu().numpy()
     fl = flops.credited(T.n_genes, hp.n, n_ic, steps)
-    v32 = solved(rp, out.status) * args.steps / wall
     # 1 % seeded sample of the series kept on the host for the parity report.
     par_ids = np.sort(np.random.default_rng(3).choice(P * n_ic, (P * n_ic) // 100, replace=False))
     x_par = out.x[torch.from_numpy(par_ids).to(out.x.device)].cpu().numpy()
@@ -476,8 +523,10 @@ def bench_core22ts(args, torch, rp, flops, inputs):
     out64 = rp.alloc_result(P * n_ic, T.n_genes, rp.FP64, n_t=101)
     f64 = lambda: rp.integrate(T, dp, tk, o64, out=out64, stream=stream)
     f64()
-    w64, _ = timed(f64, 1, stream, torch)
-    v64 = solved(rp, out64.status) / w64
+    w64, l64 = timed(f64, 1, stream, torch, before_last=lambda: rp.fill_sentinels(out64))
+    v64 = solved(rp, out64) / w64
+    steps64 = out64.n_acc.cpu().numpy().astype(np.int64) + out64.n_rej.cpu().numpy()
+    fl64 = flops.credited(T.n_genes, hp.n, n_ic, steps64)
     del out64
     nbytes = flops.algorithmic_bytes(T.n_genes, T.n_edges, P, n_ic, 4, n_t=101)
     rec = base_record(args)
@@ -489,13 +538,17 @@ def bench_core22ts(args, torch, rp, flops, inputs):
                              "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                              "frac": fl / (lat.mean() * 1e-3) / PEAK_FP32,
                              "frac_of_unpacked_fma_peak": fl / (lat.mean() * 1e-3) / PEAK_FP32_UNPACKED,
-                             "traffic": None,
+                             "traffic": measured_traffic("core22ts_fp32"),
+                             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                              "algorithmic_bytes_per_launch": nbytes,
                              "hbm_frac": nbytes / (lat.mean() * 1e-3) / PEAK_HBM},
-                "plain_fp64": {"value": v64, "unit": "solves/s"},
+                "plain_fp64": {"value": v64, "unit": "solves/s", "ms": float(l64.mean()),
+                               "credited_fp64_tflops": fl64 / (l64.mean() * 1e-3) / 1e12,
+                               "frac_of_fp64_peak": fl64 / (l64.mean() * 1e-3) / PEAK_FP64},
                 "speedup_fp32_vs_fp64": v32 / v64})
     if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_oracle(topo, 2004, P, n_ic, 1000, {"ss_rtol": 1e-5}, t_out=tk)
+        rec["cpu_baseline"] = cpu_oracle(topo, 2004, P, n_ic, 1000, {"ss_rtol": 1e-5}, t_out=tk,
+                                         target_s=args.cpu_seconds)
         rec["parity"] = parity_report(topo, 2004, P, n_ic, par_ids, x_par, {"ss_rtol": 1e-5}, t_out=tk)
     return rec
 
@@ -560,12 +613,19 @@ def bench_serve(args, torch, rp, flops, inputs):
     return rec
 
 
+EXTRA_DROP = ("metric", "n_gpus", "steps", "warmup", "higher_is_better", "scaling", "vs_baseline",
+              "dtype", "data")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="er10", choices=["er10", "ts", "uneven64", "core22ts", "serve", "ising"])
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="uneven64",
+                    choices=["er10", "ts", "uneven64", "core22ts", "serve", "ising"])
+    ap.add_argument("--no-extras", action="store_true",
+                    help="uneven64 only: skip the other configurations and serving")
     ap.add_argument("--n-sets", type=int, default=10000)
     ap.add_argument("--n-ic", type=int, default=100)
     ap.add_argument("--lanes", type=int, default=0)
@@ -573,11 +633,13 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=None)
-    ap.add_argument("--serve-warmup", type=int, default=None)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-stable-rate", type=float, default=100.0)
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle trajectories (0 = auto)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="target wall time of one CPU-oracle sample")
     ap.add_argument("--no-ceilings", action="store_true",
                     help="skip the VALU ceiling microbenchmarks (FP32 FMA, transcendentals, FP64 FMA)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -588,18 +650,36 @@ def main():
         print("bench.py runs on one GPU only: the library has no multi-GPU path (trajectories are "
               "independent, so several GPUs would each take a share of the ensemble)", file=sys.stderr)
         sys.exit(2)
-    if args.serve_requests is None:
-        args.serve_requests = 2000 if args.workload == "serve" else 300
-    if args.serve_warmup is None:
-        args.serve_warmup = 200 if args.workload == "serve" else 30
 
     import torch
     from paper_2503_18356_amd import flops, inputs
     from paper_2503_18356_amd import racipe as rp
 
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     fn = {"er10": bench_er10, "ts": bench_ts, "uneven64": bench_uneven64,
           "core22ts": bench_core22ts, "serve": bench_serve, "ising": bench_ising}[args.workload]
     rec = fn(args, torch, rp, flops, inputs)
+    if args.workload == "uneven64" and not args.no_extras:
+        extras = {}
+        for name, f in (("c2_er10_1e6", bench_er10), ("c4_core22_series_1e6", bench_core22ts),
+                        ("c1_toggle_switch_1e4", bench_ts)):
+            print(f"[bench] {name}", file=sys.stderr, flush=True)
+            r = f(args, torch, rp, flops, inputs)
+            extras[name] = {k: v for k, v in r.items() if k not in EXTRA_DROP}
+            torch.cuda.empty_cache()
+        rec["extras"] = extras
+        if not args.no_serve:
+            print("[bench] serving", file=sys.stderr, flush=True)
+            rec["serving"] = serving_run(args.serve_requests, args.serve_warmup, args.serve_rate)
+            rec["latency_ms"] = {"p50": rec["serving"]["p50_ms"], "p99": rec["serving"]["p99_ms"],
+                                 "what": "serving request latency (arrival to last trajectory done) at "
+                                         f"{args.serve_rate:g} requests/s offered, {args.serve_requests} "
+                                         f"requests after {args.serve_warmup} warm-up"}
     print(json.dumps(rec), flush=True)
 
 

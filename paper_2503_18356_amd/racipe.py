@@ -408,6 +408,30 @@ def alloc_result(n_traj: int, n_genes: int, precision: int, n_t: int = 0, device
                   torch.empty(n_traj, dtype=torch.int32, device=device))
 
 
+def fill_sentinels(res: Result) -> Result:
+    """Mark every output as not written (x NaN, t_final NaN, status -1, step
+    counts -1), so that a trajectory a solve never finished is visible."""
+    res.x.fill_(float("nan"))
+    res.t_final.fill_(float("nan"))
+    res.status.fill_(-1)
+    res.n_acc.fill_(-1)
+    res.n_rej.fill_(-1)
+    return res
+
+
+def unfinished(res: Result) -> int:
+    """Trajectories whose outputs still hold a sentinel after a solve: a
+    status outside 0..4, a negative step count, a NaN end time or a
+    non-finite state (a finished trajectory with NaN state has status
+    NONFINITE and is not counted)."""
+    import torch
+    st = res.status
+    bad = (st < 0) | (st > 4) | (res.n_acc < 0) | (res.n_rej < 0) | torch.isnan(res.t_final)
+    xbad = ~torch.isfinite(res.x.reshape(res.x.shape[0], -1)).all(dim=1)
+    bad |= xbad & (st != NONFINITE)
+    return int(bad.sum().item())
+
+
 def _info(res: Result) -> _Info:
     return _Info(res.t_final.data_ptr(), res.status.data_ptr(), res.n_acc.data_ptr(),
                  res.n_rej.data_ptr())
