@@ -306,11 +306,9 @@ def bench_er10(args, torch, rp, flops, inputs):
             "fp32_fma_tflops": 2 * c["fp32_fma"] / 1e12,
             "v_exp_f32_tops": c["v_exp_f32"] / 1e12, "v_log_f32_tops": c["v_log_f32"] / 1e12,
             "v_rcp_f32_tops": c["v_rcp_f32"] / 1e12, "fp64_fma_tflops": 2 * c["fp64_fma"] / 1e12,
-            "fp32_fma_literal_tflops": 2 * c["fp32_fma_literal"] / 1e12,
             "what": "sustained rates of one-operation kernels built like the solver kernels (no packed "
                     "FP32), all lanes of the device; fp32_fma takes its operands from registers "
-                    "(v_fma_f32, as the solver does), fp32_fma_literal has a literal multiplier "
-                    "(v_fmamk_f32)"}
+                    "(v_fma_f32, as the solver does)"}
         rec["roofline"]["frac_of_measured_fp32_fma"] = achieved / (2 * c["fp32_fma"])
     if not args.no_plain:
         o64 = rp.Opts(precision=rp.FP64, ss_rtol=1e-5, lanes_per_traj=args.lanes)
