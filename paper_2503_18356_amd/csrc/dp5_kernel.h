@@ -301,7 +301,13 @@ constexpr int requested_waves() {
         if (M == kTsit5 && EPL == 13 && GPL == 5) return 3;
         return 1;
     }
-    if (M == kDP5) return (EPL == 16 && GPL == 8) ? 2 : 1;
+    if (M == kDP5) {
+        // The 22-gene series shape (11, 3) fits four waves with 56 bytes of
+        // spill and runs 8.5 % faster than at three (25.6 -> 23.4 ms);
+        // (8, 3) takes 12 bytes.
+        if ((EPL == 11 || EPL == 8) && GPL == 3) return 4;
+        return (EPL == 16 && GPL == 8) ? 2 : 1;
+    }
     if ((EPL == 11 && GPL == 3) || (EPL == 8 && GPL == 4) || (EPL == 12 && GPL == 3) || (EPL == 16 && GPL == 2))
         return 3;
     return (EPL == 12 && GPL == 8) ? 2 : 1;
