@@ -412,10 +412,32 @@ def bench_uneven64(args, torch, rp, flops, inputs):
     t_sample = time.time() - t0
     n_traj = sum(P * 10 for P in Ps)
     stream = torch.cuda.current_stream()
-    o32 = rp.Opts(precision=rp.FP32)
+    o32 = rp.Opts(precision=rp.FP32, lanes_per_traj=args.lanes, refill_min=args.refill_min)
     outs = [rp.alloc_result(p.n_sets * 10, T.n_genes, rp.FP32) for T, p in items]
     fill = lambda: [rp.fill_sentinels(o) for o in outs]
-    fn = lambda: rp.steady_states_batch([(T, p, o) for (T, p), o in zip(items, outs)], o32, stream=stream)
+    # Lane counts and refill batches: the library's cost model (default), and
+    # the autotuner's per-network measurements (chosen form).
+    knobs = [(0, 0)] * len(items)
+    tune_rec = None
+    if not args.no_tune and args.lanes == 0 and args.refill_min == 0:
+        import tempfile
+        from paper_2503_18356_amd.autotune import Autotuner
+        tu = Autotuner(os.path.join(tempfile.gettempdir(), f"racipe_autotune_{os.getpid()}.json"))
+        t_tune = time.time()
+        choices = tu.tune_batch(Ts, rp.FP32, n_sets=4000, n_ic=10)
+        t_tune = time.time() - t_tune
+        knobs = [(c.lanes, c.refill_min) for c in choices]
+        run_d = lambda: rp.steady_states_batch([(T, p, o) for (T, p), o in zip(items, outs)], o32, stream=stream)
+        run_d()
+        wall_d, lat_d = timed(run_d, args.steps, stream, torch, before_last=fill)
+        tune_rec = {"seconds": t_tune, "sample": "4000 sets x 10 ICs per network bucket, HIP-event timed",
+                    "default_value": sum(solved(rp, o) for o in outs) * args.steps / wall_d,
+                    "default_ms": float(lat_d.mean()),
+                    "choices": [{"N": T.n_genes, "E": T.n_edges, "lanes_default": T.auto_lanes(rp.FP32),
+                                 "lanes": c.lanes, "refill_min": c.refill_min, "shape": list(T.shape(c.lanes))}
+                                for T, c in zip(Ts, choices)]}
+    fn = lambda: rp.steady_states_batch([(T, p, o, k) for (T, p), o, k in zip(items, outs, knobs)], o32,
+                                        stream=stream)
     for _ in range(max(1, args.warmup)):
         fn()
     wall, lat = timed(fn, args.steps, stream, torch, before_last=fill)
@@ -455,6 +477,9 @@ def bench_uneven64(args, torch, rp, flops, inputs):
         "steps_per_solve": float(np.concatenate(steps_all).mean()),
         "device_sampling_s": t_sample,
     })
+    if tune_rec is not None:
+        tune_rec["tuned_over_default"] = v32 / tune_rec["default_value"]
+        rec["autotune"] = tune_rec
     if not args.no_plain:
         o64 = rp.Opts(precision=rp.FP64, ss_rtol=1e-5)
         outs64 = [rp.alloc_result(p.n_sets * 10, T.n_genes, rp.FP64) for T, p in items]
@@ -629,6 +654,8 @@ def main():
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--refill-min", type=int, default=0)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="uneven64: the library's lane model instead of the autotuner's choices")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)

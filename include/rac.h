@@ -319,13 +319,21 @@ typedef struct {
     int32_t n_ic;
     void* x_out;             /* device [P * n_ic][N] */
     rac_traj_info info;      /* device arrays */
+    int32_t lanes_per_traj;  /* 0: as opts; else this network's lane count
+                                (a power of two <= 64, e.g. an autotuner's) */
+    int32_t refill_min;      /* 0: as opts; else the refill batch of the launch
+                                that takes this network (the largest asked by
+                                the networks sharing a launch) */
 } rac_batch_item;
 
 /* Steady states of several networks of uneven size in persistent launches
- * that pull trajectories from one device work queue (networks sharing a
- * kernel shape go into the same launch; lanes freed by converged trajectories
- * are refilled from the queue).  Results per item are as rac_steady_states
- * with the same opts.  EINVAL as rac_steady_states for any item. */
+ * that pull trajectories from one device work queue (networks sharing a lane
+ * count and kernel shape go into the same launch; lanes freed by converged
+ * trajectories are refilled from the queue; launches overlap on side streams
+ * forked from and joined into hip_stream).  Results per item are as
+ * rac_steady_states with the same opts and the item's lane count.  EINVAL as
+ * rac_steady_states for any item, or a lane count that is not 0 or a power
+ * of two <= 64, or refill_min < 0. */
 rac_status rac_steady_states_batch(const rac_batch_item* items, int32_t n_items,
                                    const rac_solver_opts* opts, void* hip_stream);
 

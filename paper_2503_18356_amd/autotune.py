@@ -1,12 +1,15 @@
 """Autotuner for the launch knobs of the DP5 kernel.
 
-Knobs: lanes per trajectory (which also fixes the lane plan and therefore the
-compiled register/LDS shape) and the refill batch (how many trajectory groups
-of a wave must be free before it pulls new work).  For a network it times
-short solves of a parameter-set sample at every feasible combination and
-keeps the fastest.  Choices are cached as JSON per (GPU architecture,
-precision, network bucket), where the bucket is (N, E, largest in-degree)
-rounded up to powers of two, so similar networks reuse a measurement.
+Knobs: lanes per trajectory, which fixes the lane plan and with it the
+compiled kernel shape (edge slots and gene slots per lane: the register
+budget and the per-wave LDS tile), and the refill batch (how many trajectory
+groups of a wave must be free before it pulls new work).  For a network it
+times solves of a parameter-set sample at every feasible combination, with
+HIP events on the launch stream, and keeps the fastest.  Choices are cached
+as JSON per (GPU architecture, precision, network bucket), where the bucket
+is (N, E, largest in-degree) rounded up to powers of two, so similar
+networks reuse a measurement; tune_batch() gives the per-network choices
+that rac_steady_states_batch takes per item.
 """
 from __future__ import annotations
 
@@ -69,27 +72,33 @@ class Autotuner:
         for lanes in LANES:
             if T.lanes_supported(lanes, precision):
                 groups = 64 // lanes
-                for rm in sorted({1, max(1, groups // 8), max(1, groups // 4), max(1, groups // 2)}):
+                for rm in sorted({max(1, groups // 8), max(1, groups // 4), max(1, groups // 2), groups}):
                     out.append((lanes, rm))
         return out
 
-    def measure(self, T, precision: int, n_sets: int = 2000, n_ic: int = 10, seed: int = 1,
+    def measure(self, T, precision: int, n_sets: int = 4000, n_ic: int = 10, seed: int = 1,
                 reps: int = 2, opts: rp.Opts | None = None) -> list[Choice]:
+        """Time every candidate on a sample of n_sets x n_ic trajectories:
+        HIP events on the launch stream around each solve, best of `reps`
+        after one untimed run."""
         import torch
         params = rp.sample_params(T, seed, n_sets, n_ic).to_device()
         base = opts or rp.Opts(precision=precision)
+        stream = torch.cuda.current_stream()
         res = []
         out = None
         for lanes, rm in self.candidates(T, precision):
             o = rp.Opts(**{**base.__dict__, "precision": precision, "lanes_per_traj": lanes,
                            "refill_min": rm})
+            out = rp.steady_states(T, params, o, out=out, stream=stream)
             best = float("inf")
-            for _ in range(reps + 1):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                out = rp.steady_states(T, params, o, out=out)
-                torch.cuda.synchronize()
-                best = min(best, time.perf_counter() - t0)
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                rp.steady_states(T, params, o, out=out, stream=stream)
+                e1.record(stream)
+                e1.synchronize()
+                best = min(best, e0.elapsed_time(e1) * 1e-3)
             res.append(Choice(lanes, rm, n_sets * n_ic / best))
         return res
 
@@ -108,6 +117,10 @@ class Autotuner:
                            "all": [[c.lanes, c.refill_min, c.solves_per_s] for c in results]}
         self.save()
         return best
+
+    def tune_batch(self, topos, precision: int = rp.FP32, **kw) -> list[Choice]:
+        """Choices for every network of a batch (one measurement per bucket)."""
+        return [self.tune(t, precision, **kw) for t in topos]
 
     def opts(self, topo, precision: int = rp.FP32, base: rp.Opts | None = None, **kw) -> rp.Opts:
         c = self.tune(topo, precision, **kw)

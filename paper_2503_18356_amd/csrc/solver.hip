@@ -190,6 +190,8 @@ struct Job {
     int32_t n_ic;
     void* x_out;
     rac_traj_info info;
+    int32_t lanes = 0;   // 0: from the options
+    int32_t refill = 0;  // 0: from the options
 };
 
 int pick_lanes(const rac_topology* t, const rac_solver_opts* o) {
@@ -330,6 +332,9 @@ rac_status launch_group(const std::vector<Job>& jobs, int lpt, const rac_solver_
     a.gpl = gpl;
     a.n_t = ts ? n_t : 0;
     a.c = make_controls(o, n_groups);
+    int refill = 0;
+    for (const Job& j : jobs) refill = std::max(refill, j.refill);
+    if (refill > 0) a.c.refill_min = refill;
 
     // Per-call device block: queue counter, network table, output times.
     const size_t off_nets = 256;
@@ -363,7 +368,7 @@ rac_status run_jobs(std::vector<Job>& jobs, const rac_solver_opts* o, bool ts,
     std::map<std::tuple<int, int, int>, std::vector<Job>> groups;
     for (const Job& j : jobs) {
         if (j.params.n_sets == 0) continue;
-        const int lpt = pick_lanes(j.topo, o);
+        const int lpt = j.lanes > 0 ? j.lanes : pick_lanes(j.topo, o);
         if (lpt == 0 || !plan_fits(j.topo, lpt, o->precision))
             return fail(RAC_EUNSUPPORTED, "network (N=" + std::to_string(j.topo->n_genes) + ", E=" +
                                               std::to_string(j.topo->n_edges) +
@@ -557,7 +562,13 @@ rac_status rac_steady_states_batch(const rac_batch_item* items, int32_t n_items,
         const rac_batch_item& it = items[i];
         st = check_item(it.topo, &it.params, it.ic, it.n_ic, it.x_out, "rac_steady_states_batch");
         if (st != RAC_OK) return st;
-        jobs.push_back({it.topo, it.params, it.ic, it.n_ic, it.x_out, it.info});
+        if (it.lanes_per_traj < 0 || it.lanes_per_traj > kWave || (it.lanes_per_traj & (it.lanes_per_traj - 1)))
+            return fail(RAC_EINVAL, "rac_steady_states_batch: item lanes_per_traj must be 0 or a power of two <= 64");
+        if (it.refill_min < 0) return fail(RAC_EINVAL, "rac_steady_states_batch: item refill_min < 0");
+        Job j{it.topo, it.params, it.ic, it.n_ic, it.x_out, it.info};
+        j.lanes = it.lanes_per_traj;
+        j.refill = it.refill_min;
+        jobs.push_back(j);
     }
     return run_jobs(jobs, opts, false, nullptr, 0, hip_stream);
 }

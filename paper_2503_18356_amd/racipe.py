@@ -71,7 +71,8 @@ class _Info(C.Structure):
 
 class _BatchItem(C.Structure):
     _fields_ = [("topo", C.c_void_p), ("params", _ParamsView), ("ic", C.c_void_p),
-                ("n_ic", C.c_int32), ("x_out", C.c_void_p), ("info", _Info)]
+                ("n_ic", C.c_int32), ("x_out", C.c_void_p), ("info", _Info),
+                ("lanes_per_traj", C.c_int32), ("refill_min", C.c_int32)]
 
 
 _lib = None
@@ -483,17 +484,20 @@ def integrate(topo: Topology, params: DeviceParams, t_out, opts: Opts | None = N
 
 
 def steady_states_batch(items, opts: Opts | None = None, stream=None) -> list[Result]:
-    """items: list of (Topology, DeviceParams[, Result]).  One fused launch per
-    kernel shape; returns the Results."""
+    """items: list of (Topology, DeviceParams[, Result[, (lanes, refill_min)]]).
+    One fused launch per lane count and kernel shape; returns the Results.
+    The optional pair overrides the options' lane count and refill batch for
+    that network (0 keeps the options')."""
     opts = opts or Opts()
     outs, arr = [], (_BatchItem * max(len(items), 1))()
     for i, it in enumerate(items):
         topo, prm = it[0], it[1]
         out = it[2] if len(it) > 2 and it[2] is not None else alloc_result(
             prm.n_sets * prm.n_ic, topo.n_genes, opts.precision, device=prm.G.device)
+        lanes, refill = it[3] if len(it) > 3 and it[3] is not None else (0, 0)
         outs.append(out)
         arr[i] = _BatchItem(topo.handle.value, prm.view(), prm.ic.data_ptr(), prm.n_ic,
-                            out.x.data_ptr(), _info(out))
+                            out.x.data_ptr(), _info(out), int(lanes), int(refill))
     o = opts.c()
     _check(lib().rac_steady_states_batch(arr, len(items), C.byref(o), _stream_ptr(stream)))
     return outs
