@@ -285,9 +285,10 @@ rac_status rac_steady_states(const rac_topology* topo, const rac_params_view* de
 /* rac_steady_states for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): the same arguments, kernels and results, bit for bit, but no
- * device allocation or free.  The queue counter and the network descriptor
- * live in a library-owned device scratch array of 1024 bytes per GPU (the
- * counter and one descriptor: one network per call), kept until the process
+ * device allocation or free.  The work-queue counters (one per XCD) and the
+ * network descriptor live in a library-owned device scratch array of 4096
+ * bytes per GPU (the counters and one descriptor: one network per call), kept
+ * until the process
  * ends and cleared by a kernel at the start of every call.  Calls that
  * overlap on one GPU (concurrent streams or threads) share that scratch and
  * race: order them on one stream.  The network's lane plan for the lane count

@@ -402,9 +402,25 @@ void dp5_kernel(LaunchArgs a) {
     const double t_stop = TS ? a.t_out[a.n_t - 1] : c.t_end;  // the same for every trajectory
     bool exhausted = false;   // queue drained and no claimed index left
     bool drained = false;     // the shared queue has nothing left to pop
+    // Sub-queue this wave pops from (persistent launches): its XCD's range
+    // first, then the following ones; tried counts the ranges found empty.
+    const int home = (int)(blockIdx.x % kSubQueues);
+    int q = home, tried = 0;
+    // Sub-queue x holds the granules g of kGranule consecutive trajectories
+    // with g % kSubQueues == x; positions count within a sub-queue.
+    auto q_count = [&](int x) -> uint64_t {
+        const uint64_t n = (uint64_t)a.total, ng = n / kGranule, rem = n % kGranule;
+        return (ng / kSubQueues + ((uint64_t)x < ng % kSubQueues ? 1 : 0)) * kGranule +
+               ((uint64_t)x == ng % kSubQueues ? rem : 0);
+    };
+    auto q_index = [&](int x, uint64_t pos) -> int64_t {
+        return (int64_t)(((pos / kGranule) * kSubQueues + (uint64_t)x) * kGranule + pos % kGranule);
+    };
     uint64_t popped = 0;      // queue position after this wave's last pop
-    // Indices this wave has claimed but not started: [claim_next, claim_end).
+    // Positions this wave has claimed but not started: [claim_next, claim_end)
+    // of sub-queue claim_q.
     uint64_t claim_next = 0, claim_end = 0;
+    int claim_q = home;
     // The group's network (index, N, 1/N), kept in LDS rather than registers.
     Rec* const rec = reinterpret_cast<Rec*>(lb + (wave_elem + Lay::kRec) * SZ + sizeof(Rec) * lane);
     rec->inv_n = 1.0;
@@ -665,12 +681,14 @@ void dp5_kernel(LaunchArgs a) {
             const uint64_t free_lead = __ballot(traj < 0 && r == 0);
             const int nfree = __popcll(free_lead);
             const uint64_t busy_lead = __ballot(traj >= 0 && r == 0);
+            // End of the range popped from: the serving queue's tail, or the
+            // current sub-queue's end.
             const uint64_t total =
                 BOUNDED ? __hip_atomic_load(&a.ctl->total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                        : (uint64_t)a.total;
+                        : q_count(q);
             // Refill in batches (each refill costs the wave two extra right-hand
-            // sides), but take single items once the queue is nearly drained.
-            const uint64_t n_waves = (uint64_t)gridDim.x * (kBlock / 64);
+            // sides), but take single items once the range is nearly drained.
+            const uint64_t n_waves = (uint64_t)gridDim.x * (kBlock / 64) / (BOUNDED ? 1 : kSubQueues) + 1;
             const bool near_end = popped >= total || total - popped < n_waves * 64;
             if (nfree > 0 && (nfree >= c.refill_min || busy_lead == 0 || near_end)) {
                 // Serve from this wave's claimed indices first; pop the rest
@@ -683,38 +701,68 @@ void dp5_kernel(LaunchArgs a) {
                                                                                  : (uint64_t)nfree;
                 const uint64_t need = (uint64_t)nfree - local_n;
                 unsigned long long base = 0, got = 0;
+                int pop_q = q;
                 if (need > 0 && !drained) {
                     const bool claim = !BOUNDED && total - popped > n_waves * (uint64_t)c.chunk * 2 &&
                                        popped < total;
                     const uint64_t want = claim && need < (uint64_t)c.chunk ? (uint64_t)c.chunk : need;
-                    if (lane == 0) {
-                        // One atomic per wave.  In step batches head may run
-                        // past total; the batch's last graph node clamps it
-                        // back before the host appends more, so appended
-                        // indices are served.
-                        base = atomicAdd(a.counter, (unsigned long long)want);
-                        got = base >= total ? 0ull
-                                            : (base + (unsigned long long)want <= total ? (unsigned long long)want
-                                                                                       : total - base);
+                    if (BOUNDED) {
+                        if (lane == 0) {
+                            // One atomic per wave.  In step batches head may run
+                            // past total; the batch's last graph node clamps it
+                            // back before the host appends more, so appended
+                            // indices are served.
+                            base = atomicAdd(a.counter, (unsigned long long)want);
+                            got = base >= total ? 0ull
+                                                : (base + (unsigned long long)want <= total ? (unsigned long long)want
+                                                                                           : total - base);
+                        }
+                        base = uniform64(__shfl(base, 0));
+                        got = uniform64(__shfl(got, 0));
+                        popped = base + got;
+                        if (base + want >= total || got < want) drained = true;
+                    } else {
+                        // Pop from sub-queue q; a range found exhausted sends
+                        // the wave on to the next one (at most kSubQueues
+                        // attempts per pop, one atomic each).
+                        for (;;) {
+                            const uint64_t q_end = q_count(q);
+                            pop_q = q;
+                            if (lane == 0) {
+                                base = atomicAdd(a.counter + q * kCounterStride, (unsigned long long)want);
+                                got = base >= q_end ? 0ull
+                                                    : (base + (unsigned long long)want <= q_end ? (unsigned long long)want
+                                                                                                : q_end - base);
+                            }
+                            base = uniform64(__shfl(base, 0));
+                            got = uniform64(__shfl(got, 0));
+                            popped = base + got;
+                            if (base + want >= q_end || got < want) {
+                                if (++tried >= kSubQueues) {
+                                    drained = true;
+                                } else {
+                                    q = q + 1 == kSubQueues ? 0 : q + 1;
+                                    popped = 0;
+                                }
+                            }
+                            if (got > 0 || drained) break;
+                        }
                     }
-                    base = uniform64(__shfl(base, 0));
-                    got = uniform64(__shfl(got, 0));
-                    popped = base + got;
-                    if (base + want >= total || got < want) drained = true;
                 }
                 if (traj < 0) {
                     const uint64_t rank = (uint64_t)__popcll(free_lead & ((1ull << gshift) - 1ull));
                     if (rank < local_n) {
-                        load_traj((int64_t)(claim_next + rank));
+                        load_traj(BOUNDED ? (int64_t)(claim_next + rank) : q_index(claim_q, claim_next + rank));
                     } else if (rank - local_n < (uint64_t)got) {
-                        const uint64_t idx = (uint64_t)base + (rank - local_n);
-                        if (idx < total) load_traj((int64_t)idx);
+                        const uint64_t pos = (uint64_t)base + (rank - local_n);
+                        load_traj(BOUNDED ? (int64_t)pos : q_index(pop_q, pos));
                     }
                 }
                 claim_next += local_n;
                 if (got > need) {
                     claim_next = (uint64_t)base + need;
                     claim_end = (uint64_t)base + got;
+                    claim_q = pop_q;
                 }
                 if (drained && claim_next >= claim_end) exhausted = true;
             }

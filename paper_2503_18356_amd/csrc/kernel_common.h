@@ -73,7 +73,7 @@ struct LaunchArgs {
     const NetDesc* nets;
     int32_t n_nets;
     int64_t total;        // trajectories over all networks
-    unsigned long long* counter;
+    unsigned long long* counter;  // kSubQueues counters (serving: one, the queue head)
     int32_t lpt, epl, gpl;  // lanes per trajectory; runtime slot bounds
     const double* t_out;    // device, time-series mode
     int32_t n_t;
@@ -85,6 +85,20 @@ struct LaunchArgs {
 };
 
 constexpr int kBlock = 256;  // 4 independent waves per block
+
+// Persistent launches split their work queue into one sub-queue per XCD
+// (workgroups go to the 8 XCDs of an MI355X round robin, so block b runs on
+// XCD b % 8): sub-queue x serves the granules of kGranule consecutive
+// trajectories whose index is x modulo 8, so the parameter rows a granule
+// reads stay in one XCD's L2 while every sub-queue holds a fair sample of the
+// work; a wave pops from its own XCD's sub-queue and then steals from the
+// following ones.  The counters count positions within their sub-queue.
+constexpr int kSubQueues = 8;
+constexpr uint64_t kGranule = 2048;
+// Each counter has a 256-byte line of its own (atomics from different XCDs on
+// one line would contend); the counters take kCounterBytes.
+constexpr int kCounterStride = 32;  // in u64
+constexpr size_t kCounterBytes = (size_t)kSubQueues * kCounterStride * 8;
 
 // Bytes of saved state per wave between serving step batches (x and k1 per
 // gene slot, then t, h, trajectory id, step counts and flags per lane).

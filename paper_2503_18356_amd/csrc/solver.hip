@@ -134,14 +134,12 @@ void free_device_plans(rac_topology* t) {
 
 namespace {
 
-// Zero the queue counter with a kernel (no memset node in captured graphs).
-// Zero the queue counter and, for a single network, store its descriptor
-// (no host copy for the common one-network launch).
+// Zero the sub-queue counters and, for a single network, store its
+// descriptor (a kernel, not a memset: no memset node in captured graphs, and
+// no host copy for the common one-network launch).
 __global__ void setup_launch(unsigned long long* counter, NetDesc* table, NetDesc one) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        *counter = 0ull;
-        if (table) *table = one;
-    }
+    if (blockIdx.x == 0 && threadIdx.x < kSubQueues) counter[threadIdx.x * kCounterStride] = 0ull;
+    if (threadIdx.x == 0 && blockIdx.x == 0 && table) *table = one;
 }
 
 rac_status check_opts(const rac_solver_opts* o, const char* who) {
@@ -336,8 +334,8 @@ rac_status launch_group(const std::vector<Job>& jobs, int lpt, const rac_solver_
     for (const Job& j : jobs) refill = std::max(refill, j.refill);
     if (refill > 0) a.c.refill_min = refill;
 
-    // Per-call device block: queue counter, network table, output times.
-    const size_t off_nets = 256;
+    // Per-call device block: queue counters, network table, output times.
+    const size_t off_nets = kCounterBytes;
     const size_t off_t = off_nets + (descs.size() * sizeof(NetDesc) + 255) / 256 * 256;
     const size_t bytes = off_t + (ts ? sizeof(double) * n_t : 0);
     void* blk = fixed_block;
@@ -434,8 +432,8 @@ rac_status run_jobs(std::vector<Job>& jobs, const rac_solver_opts* o, bool ts,
 // own copy for the life of the process; in host code the array's name is
 // only a stand-in, so its device address is looked up once per device and
 // used everywhere instead.
-constexpr size_t kNoAllocScratchBytes = 1024;
-static_assert(256 + sizeof(NetDesc) <= kNoAllocScratchBytes, "scratch holds the counter and one descriptor");
+constexpr size_t kNoAllocScratchBytes = 4096;
+static_assert(kCounterBytes + sizeof(NetDesc) <= kNoAllocScratchBytes, "scratch holds the counters and one descriptor");
 __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 rac_status scratch_address(int dev, char** out) {
