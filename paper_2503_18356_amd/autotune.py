@@ -4,12 +4,20 @@ Knobs: lanes per trajectory, which fixes the lane plan and with it the
 compiled kernel shape (edge slots and gene slots per lane: the register
 budget and the per-wave LDS tile), and the refill batch (how many trajectory
 groups of a wave must be free before it pulls new work).  For a network it
-times solves of a parameter-set sample at every feasible combination, with
-HIP events on the launch stream, and keeps the fastest.  Choices are cached
-as JSON per (GPU architecture, precision, network bucket), where the bucket
-is (N, E, largest in-degree) rounded up to powers of two, so similar
-networks reuse a measurement; tune_batch() gives the per-network choices
-that rac_steady_states_batch takes per item.
+measures every combination within a factor of two of the library's lane
+model and keeps the fastest.  What is measured is the marginal throughput
+with the GPU full: solves of n and 2n trajectories, n twice what the GPU
+holds resident at that lane count, timed with HIP events on the launch
+stream, give 1 / (per-trajectory cost) = n / (t(2n) - t(n)).  The difference
+cancels the launch cost and the drain at the end of a launch, which a
+network inside a large batch does not pay on its own; a plain timing of a
+small sample counts them and so favours more lanes per trajectory than a
+full GPU wants.  Choices are cached as JSON per (GPU architecture,
+precision, network bucket), where the bucket is (N, E, largest in-degree)
+rounded up to powers of two, so similar networks reuse a measurement;
+tune_batch() gives the per-network choices that rac_steady_states_batch
+takes per item, and pick_faster() checks them against the lane model on
+the real batch.
 """
 from __future__ import annotations
 
@@ -25,6 +33,9 @@ from . import racipe as rp
 DEFAULT_CACHE = os.environ.get("RACIPE_AUTOTUNE_CACHE",
                                os.path.join(os.path.expanduser("~"), ".cache", "racipe", "autotune.json"))
 LANES = (1, 2, 4, 8, 16, 32, 64)
+# Waves the GPU holds resident at the usual occupancy (256 CUs x 4 SIMDs x 4
+# waves per SIMD): the measured samples are sized against it.
+RESIDENT_WAVES = 4096
 
 
 def _pow2(v: int) -> int:
@@ -67,30 +78,29 @@ class Autotuner:
             json.dump(self.cache, f, indent=1, sort_keys=True)
         os.replace(tmp, self.path)
 
-    def candidates(self, T, precision: int):
+    def candidates(self, T, precision: int, span: int = 2):
+        """(lanes, refill) pairs: lane counts within a factor `span` of the
+        lane model's choice, each with four refill batches."""
+        d = T.auto_lanes(precision)
         out = []
         for lanes in LANES:
-            if T.lanes_supported(lanes, precision):
+            if d // span <= lanes <= d * span and T.lanes_supported(lanes, precision):
                 groups = 64 // lanes
                 for rm in sorted({max(1, groups // 8), max(1, groups // 4), max(1, groups // 2), groups}):
                     out.append((lanes, rm))
         return out
 
-    def measure(self, T, precision: int, n_sets: int = 4000, n_ic: int = 10, seed: int = 1,
-                reps: int = 2, opts: rp.Opts | None = None) -> list[Choice]:
-        """Time every candidate on a sample of n_sets x n_ic trajectories:
-        HIP events on the launch stream around each solve, best of `reps`
-        after one untimed run."""
+    def measure(self, T, precision: int, n_ic: int = 10, seed: int = 1, reps: int = 2,
+                opts: rp.Opts | None = None, n_sets: int | None = None, span: int = 2) -> list[Choice]:
+        """Marginal solves/s of every candidate: best of `reps` HIP-event
+        timings of n and of 2n trajectories after one untimed run, with n =
+        2 x RESIDENT_WAVES x 64 / lanes (or n_sets x n_ic when given)."""
         import torch
-        params = rp.sample_params(T, seed, n_sets, n_ic).to_device()
         base = opts or rp.Opts(precision=precision)
         stream = torch.cuda.current_stream()
-        res = []
-        out = None
-        for lanes, rm in self.candidates(T, precision):
-            o = rp.Opts(**{**base.__dict__, "precision": precision, "lanes_per_traj": lanes,
-                           "refill_min": rm})
-            out = rp.steady_states(T, params, o, out=out, stream=stream)
+        dev = torch.device("cuda", torch.cuda.current_device())
+
+        def timed(params, o, out):
             best = float("inf")
             for _ in range(reps):
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -99,7 +109,26 @@ class Autotuner:
                 e1.record(stream)
                 e1.synchronize()
                 best = min(best, e0.elapsed_time(e1) * 1e-3)
-            res.append(Choice(lanes, rm, n_sets * n_ic / best))
+            return best
+
+        res = []
+        per_lanes = {}
+        for lanes, rm in self.candidates(T, precision, span):
+            if lanes not in per_lanes:
+                s1 = n_sets or -(-2 * RESIDENT_WAVES * (64 // lanes) // n_ic)
+                p1 = rp.sample_params_device(T, seed, s1, n_ic)
+                p2 = rp.sample_params_device(T, seed, 2 * s1, n_ic)
+                out = rp.alloc_result(2 * s1 * n_ic, T.n_genes, precision, device=dev)
+                per_lanes[lanes] = (p1, p2, out)
+            p1, p2, out = per_lanes[lanes]
+            o = rp.Opts(**{**base.__dict__, "precision": precision, "lanes_per_traj": lanes,
+                           "refill_min": rm})
+            rp.steady_states(T, p2, o, out=out, stream=stream)
+            t1, t2 = timed(p1, o, out), timed(p2, o, out)
+            n1 = p1.n_sets * n_ic
+            # A difference lost in timing noise falls back to the plain rate.
+            rate = n1 / (t2 - t1) if t2 > 1.2 * t1 else 2 * n1 / t2
+            res.append(Choice(lanes, rm, rate))
         return res
 
     def tune(self, topo, precision: int = rp.FP32, force: bool = False, **kw) -> Choice:
@@ -127,3 +156,15 @@ class Autotuner:
         b = base or rp.Opts(precision=precision)
         return rp.Opts(**{**b.__dict__, "precision": precision, "lanes_per_traj": c.lanes,
                           "refill_min": c.refill_min})
+
+    @staticmethod
+    def pick_faster(run, tuned, default, reps: int = 2):
+        """Whichever of two per-item knob lists runs a whole batch faster:
+        run(knobs) solves the batch once and returns its seconds.  The batch
+        is the final judge because per-network measurements miss how the
+        networks share launches; each list is run once untimed first."""
+        t = {}
+        for name, knobs in (("default", default), ("tuned", tuned)):
+            run(knobs)
+            t[name] = min(run(knobs) for _ in range(reps))
+        return (tuned if t["tuned"] < t["default"] else default), t

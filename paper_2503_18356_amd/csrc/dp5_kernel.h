@@ -125,17 +125,36 @@ template <>
 struct Ops<double> {
     using NType = int;
     __device__ static int to_n(float n) { return (int)n; }
-    // Sources publish their level, edges keep 1/T; (x/T)^n by squaring.
+    // Sources publish their level, edges keep 1/T; (x/T)^n by squaring, the
+    // three low bits of n (Table 1's 1..6) by selects without a branch and
+    // any higher bits in a loop that lanes with n < 8 skip.
     __device__ static double publish(double v) { return v > 0.0 ? v : 0.0; }
     __device__ static double edge_t(double T, float) { return 1.0 / T; }
     __device__ static double hill(double xs, double invT, int n, double b, double d) {
         const double q = xs * invT;
-        double r = 1.0, base = q;
-        for (int e = n; e > 0; e >>= 1) {
-            if (e & 1) r *= base;
-            base *= base;
+        const double q2 = q * q, q4 = q2 * q2;
+        double r = (n & 1) ? q : 1.0;
+        r = (n & 2) ? r * q2 : r;
+        r = (n & 4) ? r * q4 : r;
+        if (n >= 8) {
+            double base = q4 * q4;
+            for (int e = n >> 3; e > 0; e >>= 1) {
+                if (e & 1) r *= base;
+                base *= base;
+            }
         }
-        return fma(d, 1.0 / (1.0 + r), b);
+        return fma(d, recip(1.0 + r), b);
+    }
+    // 1/v for v >= 1: the hardware estimate and two Newton steps (each
+    // squares the relative error; the estimate's is far below 2^-13, so two
+    // reach the last bit up to rounding).  v is capped at 2^1000 first, so
+    // an infinite v gives 2^-1000 (a factor b to double precision) instead
+    // of the NaN the Newton step would make of 0 * inf.
+    __device__ static double recip(double v) {
+        v = __builtin_fmin(v, 0x1p1000);
+        double y = __builtin_amdgcn_rcp(v);
+        y = fma(y, fma(-v, y, 1.0), y);
+        return fma(y, fma(-v, y, 1.0), y);
     }
     __device__ static double rcp(double v) { return 1.0 / v; }
     __device__ static double abs(double v) { return __builtin_fabs(v); }
@@ -156,7 +175,7 @@ struct OpsRealN : Ops<double> {
     __device__ static float to_n(float n) { return n; }
     __device__ static double hill(double xs, double invT, float n, double b, double d) {
         const double r = ::exp((double)n * ::log(xs * invT));
-        return fma(d, 1.0 / (1.0 + r), b);
+        return fma(d, recip(1.0 + r), b);
     }
 };
 template <typename R, bool REALN>
@@ -286,9 +305,14 @@ struct alignas(2 * sizeof(R)) RatePair {
 // would spill more are not asked: their reloads inside the step loop cost
 // more than the wave (the DP5 22-gene series at four waves with 120 bytes of
 // spill runs 20 % slower).
-template <typename R, int EPL, int GPL, bool TS, bool BOUNDED, int M>
+template <typename R, int EPL, int GPL, bool TS, bool BOUNDED, int M, bool REALN>
 constexpr int requested_waves() {
-    if (sizeof(R) != 4) return 1;
+    // FP64: two waves per SIMD (the (12, 3) series shape and the 16-slot
+    // shapes compile to a few registers over 256 unasked, which leaves one
+    // wave per SIMD to hide every FP64 latency alone; asked, they spill
+    // 12-76 bytes).  Real-n kernels carry exp/log and would spill 36-204
+    // bytes, so they are left to the compiler.
+    if (sizeof(R) != 4) return REALN ? 1 : 2;
     if (BOUNDED) {  // serving step batches (DP5, steady states)
         if (EPL == 4 && GPL == 2) return 5;
         if (EPL == 12 && GPL == 2) return 4;
@@ -314,7 +338,7 @@ constexpr int requested_waves() {
 }
 
 template <typename R, int EPL, int GPL, bool TS, bool BOUNDED = false, int M = kDP5, bool REALN = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(requested_waves<R, EPL, GPL, TS, BOUNDED, M>(), 8)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(requested_waves<R, EPL, GPL, TS, BOUNDED, M, REALN>(), 8)))
 void dp5_kernel(LaunchArgs a) {
     static_assert(!(TS && BOUNDED), "serving step batches run in steady-state mode");
     static_assert(!REALN || sizeof(R) == 8, "FP32 kernels take real coefficients natively");

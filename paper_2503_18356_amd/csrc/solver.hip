@@ -427,8 +427,8 @@ rac_status run_jobs(std::vector<Job>& jobs, const rac_solver_opts* o, bool ts,
     return st;
 }
 
-// Device scratch of the call without allocation: the queue counter in the
-// first 256 bytes, the network descriptor after it.  Each device holds its
+// Device scratch of the call without allocation: the queue counters in the
+// first kCounterBytes, the network descriptor after them.  Each device holds its
 // own copy for the life of the process; in host code the array's name is
 // only a stand-in, so its device address is looked up once per device and
 // used everywhere instead.
