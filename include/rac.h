@@ -59,7 +59,12 @@ typedef enum {
     RAC_T_END = 1,          /* reached t_end (or the last output time) */
     RAC_MAX_STEPS = 2,      /* more than max_steps attempted steps */
     RAC_STEP_UNDERFLOW = 3, /* step size fell below 16 * 2^-52 * max(|t|, 1) */
-    RAC_NONFINITE = 4       /* initial state or its derivative not finite */
+    RAC_NONFINITE = 4       /* initial state or its derivative not finite; in FP32
+                               also a trajectory whose Hill-factor products FP32
+                               cannot hold (lambdas far outside Table 1: a lane's
+                               factors spanning over 2^250, or a production rate
+                               they push out of the normal range), ended at t0
+                               with x = NaN; FP64 solves it */
 } rac_traj_status;
 
 /* The paper's steady-state flag of a status (Sec. 2.1.3 and 3.1 report a flag

@@ -389,12 +389,26 @@ void dp5_kernel(LaunchArgs a) {
 
     // Edge slots: source address, threshold term (O::edge_t), n, sqrt(lam),
     // 1/sqrt(lam) - sqrt(lam).
-    // FP32 shapes of up to 16 edge slots use factors 1 + D / (1 + 2^z) with
-    // D >= 0 (no base term; every factor lies in [1, 1 + D], so a lane's
-    // running product stays below 100^16 for Table 1's lambdas).  Wider and
-    // FP64 shapes keep the symmetric form sqrt(lam) + (1/sqrt(lam) -
-    // sqrt(lam)) / (1 + r), whose factors lie in [0.1, 10].
+    // FP32 shapes of up to 16 edge slots use factors 1 + D / (1 + 2^z) (no
+    // base term; with Table 1's lambdas D >= 0 and every factor lies in
+    // [1, 1 + D], D < 100).  Wider and FP64 shapes keep the symmetric form
+    // sqrt(lam) + (1/sqrt(lam) - sqrt(lam)) / (1 + r), whose factors lie in
+    // [0.1, 10] for Table 1.
     constexpr bool kUnitBase = std::is_same<R, float>::value && EPL <= kUnitBaseMaxEpl;
+    // FP32 range, for any lambdas: with l_s = log2 of slot s's extreme factor
+    // (1 + D), a base-free lane's running product lies in an interval of
+    // width A = sum |l_s| (log2) centred on 2^(sum l_s / 2); it starts at
+    // 2^-round(sum l_s / 2) instead of 1, which centres it on 1.  The start
+    // lives in prefix[0] and cancels in every row's prefix ratio (a power of
+    // two: no rounding changes).  Reading it costs each evaluation one LDS
+    // read and one multiply (0.7 % on the 10-gene and 22-gene workloads);
+    // a read skipped by a wave-uniform branch where no lane needs it measured
+    // slower (1.5-2.5 %).  A trajectory FP32 still cannot hold (A >
+    // 250, or 126 in the symmetric form, or a production rate that the row's
+    // factors can push out of the normal range) starts with x = NaN and so
+    // ends NONFINITE at t0: that needs lambdas far outside Table 1, and FP64
+    // solves it.
+    constexpr bool kRangeCheck = std::is_same<R, float>::value;
     uint32_t e_xa[EPL];
     R e_invT[EPL], e_b[kUnitBase ? 1 : EPL], e_d[EPL];
     NT e_n[EPL];
@@ -460,7 +474,7 @@ void dp5_kernel(LaunchArgs a) {
 #pragma unroll
         for (int q = 0; q < GPL; ++q) st(pub_base + (uint32_t)q * kPubStride * SZ, O::publish(yv[q]));
         wave_sync();
-        R run = 1;
+        R run = kUnitBase ? ld(pre_base) : (R)1;
         // Chunks of up to four independent factors, then their running products.
 #pragma unroll
         for (int c0 = 0; c0 < EPL; c0 += 4) {
@@ -574,6 +588,9 @@ void dp5_kernel(LaunchArgs a) {
             // Hill coefficients: real ones when given, else the integer array.
             const float* NFp = dp->nf ? dp->nf + p : nullptr;
             const uint8_t* Np = dp->nf ? nullptr : dp->n + p;
+            // log2 range of this lane's running product: the sum and the
+            // sum of magnitudes of log2 of the slots' extreme factors.
+            float lane_s2 = 0.0f, lane_a2 = 0.0f;
             // Only the loads are conditional: padding slots take T = lam = n = 1,
             // an inhibiting sign and the sink, which the same formulas turn
             // into a factor of exactly 1 (every array element is written on
@@ -602,14 +619,23 @@ void dp5_kernel(LaunchArgs a) {
                     e_n[s] = nn;
                     e_invT[s] = nn * __builtin_amdgcn_logf(Tv);
                     e_d[s] = act ? Lv - 1.0f : 1.0f / Lv - 1.0f;
+                    const float l2 = __builtin_amdgcn_logf(1.0f + e_d[s]);
+                    lane_s2 += l2;
+                    lane_a2 += __builtin_fabsf(l2);
                 } else {
                     const R sl = O::sqrt((R)Lv);
                     e_invT[s] = O::edge_t((R)Tv, nv);
                     e_n[s] = O::to_n(nv);
                     e_b[s] = sl;
                     e_d[s] = (R)1 / sl - sl;
+                    if constexpr (kRangeCheck) lane_a2 += 0.5f * __builtin_fabsf(__builtin_amdgcn_logf(Lv));
                 }
             }
+            // Symmetric-form products range over [2^-A, 2^A]; base-free ones
+            // over an interval of width A that the start centres on 1.
+            bool out_of_range = kRangeCheck && !(lane_a2 <= (kUnitBase ? 250.0f : 126.0f));
+            if constexpr (kUnitBase)
+                st(pre_base, out_of_range ? 1.0f : __builtin_amdgcn_ldexpf(1.0f, -(int)__builtin_rintf(0.5f * lane_s2)));
             const float* Gp = dp->G + p;
             const float* Kp = dp->k + p;
             const float* icp = dp->ic + (int64_t)ci * n_genes;
@@ -633,14 +659,31 @@ void dp5_kernel(LaunchArgs a) {
                     // activation over lambda, 1/lam per activating edge
                     // (or sqrt(lam) and 1/sqrt(lam) in the symmetric form).
                     gf = Gv;
+                    // log2 of the row's smallest and largest factor products.
+                    float row_lo2 = 0.0f, row_hi2 = 0.0f;
                     for (int e = row_ptr[gene]; e < row_ptr[gene + 1]; ++e) {
                         const R lv = (R)Lp[e * P];
                         if constexpr (kUnitBase) {
                             gf *= sign[e] > 0 ? (c.divide ? (R)1 / lv : (R)1) : lv;
+                            // log2 (1 + D): log2 lam for activation, -log2 lam for inhibition.
+                            const float l2 = (sign[e] > 0 ? 1.0f : -1.0f) * __builtin_amdgcn_logf((float)lv);
+                            row_lo2 += l2 < 0.0f ? l2 : 0.0f;
+                            row_hi2 += l2 > 0.0f ? l2 : 0.0f;
                         } else {
                             const R sl = O::sqrt(lv);
                             gf *= (sign[e] > 0 && c.divide) ? (R)1 / sl : sl;
+                            if constexpr (kRangeCheck) {
+                                const float l2 = 0.5f * __builtin_fabsf(__builtin_amdgcn_logf((float)lv));
+                                row_lo2 -= l2;
+                                row_hi2 += l2;
+                            }
                         }
+                    }
+                    // G' times the row's factors must stay normal and finite.
+                    if constexpr (kRangeCheck) {
+                        const float lg = __builtin_amdgcn_logf((float)gf);
+                        if (Gv != (R)0 && !(lg + row_lo2 >= -125.0f && lg + row_hi2 <= 126.0f))
+                            out_of_range = true;
                     }
                     row = gene_row[gene];
                     u = (R)icp[gene];
@@ -655,6 +698,12 @@ void dp5_kernel(LaunchArgs a) {
                 // error and steady test are exactly 0, 0 and true, and their
                 // error scale atol + rtol is positive.
                 x[q] = real ? (c.ic_absolute ? u : u * Gv / kv) : (R)1;
+            }
+            if constexpr (kRangeCheck) {
+                if (((__ballot(out_of_range) >> gshift) & glow) != 0) {
+#pragma unroll
+                    for (int q = 0; q < GPL; ++q) x[q] = __builtin_nanf("");
+                }
             }
             t = c.t0;
             nacc = 0; nrej = 0; kout = 0; last_rej = false;

@@ -160,6 +160,61 @@ def test_steady_flags():
     assert [rp.not_steady_flag(s) for s in range(5)] == [0, 1, 1, 1, 1]
 
 
+@pytest.mark.parametrize("prec", [rp.FP32, rp.FP64])
+def test_wide_lambda_ranges(prec):
+    # Lambda ranges ten times wider than Table 1's on each side: activation up
+    # to 1e3, inhibition down to 1e-3.  FP32 at one lane per trajectory holds
+    # all 16 edges of an 8-gene network in one lane of the base-free form,
+    # whose running product then spans up to about 2^150, beyond FP32 unless
+    # it is centred; every trajectory must still match the oracle.
+    case = Case(inputs.erdos_renyi(8, 16, 1010), 91, 400, 5, lam_act_max=1e3, lam_inh_min=1e-3)
+    if prec == rp.FP32:
+        assert case.T.shape(1, rp.FP32) == (16, 8) and rp.factor_form(rp.FP32, 16) == 1
+    span = np.abs(np.log2(case.hp.lam.astype(np.float64))).sum(axis=0)
+    say("    log2 span of the lane product per set: max", float(span.max()), "mean", float(span.mean()))
+    assert span.max() > 128
+    out, ref, rep = case.check(opts_for(prec, lanes_per_traj=1 if prec == rp.FP32 else 0),
+                               label="wide lambda")
+    assert not np.any(out.status.cpu().numpy() == rp.NONFINITE)
+
+
+def test_lambda_beyond_fp32_range_ends_nonfinite():
+    # Lambdas up to 2^17 (and down to 2^-17): a lane of 16 slots spans about
+    # 16 x 15.6 bits, around the 250-bit room of the centred FP32 product
+    # (121 of these 300 sets beyond it, 155 within).
+    # Sets beyond it end NONFINITE with NaN states at t0 (FP64 solves them);
+    # sets within it match the oracle.  Sets within half a bit of the limit
+    # are not classified (the kernel sums hardware log2 values).
+    case = Case(inputs.erdos_renyi(8, 16, 1010), 92, 300, 4, lam_act_max=2.0 ** 17, lam_inh_min=2.0 ** -17)
+    opts = opts_for(rp.FP32, lanes_per_traj=1)
+    out = case.gpu(opts)
+    st = out.status.cpu().numpy()
+    x = out.x.cpu().numpy()
+    lam = case.hp.lam.astype(np.float64)
+    span = np.abs(np.log2(lam)).sum(axis=0)
+    # Every row's span (at most in-degree x 17 bits) stays far inside the
+    # production-rate check, so only the lane span decides.
+    net = case.net
+    indeg = np.bincount(np.asarray(net.dst), minlength=8)
+    assert indeg.max() * 17 < 125
+    set_of = np.arange(case.n_traj) // case.n_ic
+    beyond = span[set_of] > 250.5
+    within = span[set_of] < 249.5
+    say("    sets beyond the FP32 room:", int((span > 250.5).sum()), "within:", int((span < 249.5).sum()))
+    assert beyond.any() and within.any()
+    assert np.all(st[beyond] == rp.NONFINITE) and np.all(np.isnan(x[beyond]))
+    traj = np.flatnonzero(within)
+    oo = case.oracle_opts(opts)
+    ref = oracle.steady_states(net, case.op, oo, traj_ids=traj, n_threads=THREADS)
+    assert np.all(np.isin(ref.status, (oracle.CONVERGED, oracle.T_END)))
+    rep = parity.compare_steady(net, case.op, oo, traj, x[traj], ref.x, case.n_ic, st[traj], ref.status)
+    say("   ", rep)
+    assert rep.ok(), rep.unexcused[:10]
+    # FP64 solves the sets that FP32 cannot hold.
+    o64 = case.gpu(opts_for(rp.FP64, ss_rtol=1e-5))
+    assert not np.any(o64.status.cpu().numpy() == rp.NONFINITE)
+
+
 def test_time_series_dense_core():
     # 22-gene / 82-edge network, 101 evenly spaced outputs on [0, 100].
     case = Case(inputs.dense_core(1004), 2004, 300, 10)

@@ -78,12 +78,20 @@ def _direct(T, params, lanes):
     return out
 
 
-@pytest.mark.parametrize("batch_steps", [7, 64, 100000])
-def test_step_batches_equal_one_shot(batch_steps):
-    T = rp.Topology.from_inputs(inputs.erdos_renyi(10, 25, 1002))
-    lanes = T.auto_lanes()
+@pytest.mark.parametrize("batch_steps,wide", [(7, False), (64, False), (100000, False), (7, True)])
+def test_step_batches_equal_one_shot(batch_steps, wide):
+    # wide: lambdas ten times beyond Table 1's on each side, all 16 edges in
+    # one lane, so most lanes start their running product below 1 (the start
+    # must survive suspension between step batches).
+    if wide:
+        T = rp.Topology.from_inputs(inputs.erdos_renyi(8, 16, 1010))
+        lanes = 1
+        params = rp.sample_params(T, 93, 300, 10, ranges=rp.Ranges(lam_act_max=1e3, lam_inh_min=1e-3)).to_device()
+    else:
+        T = rp.Topology.from_inputs(inputs.erdos_renyi(10, 25, 1002))
+        lanes = T.auto_lanes()
+        params = rp.sample_params(T, 2002, 300, 10).to_device()
     epl, gpl = T.shape(lanes)
-    params = rp.sample_params(T, 2002, 300, 10).to_device()
     ref = _direct(T, params, lanes)
     srv = rp.StepServer(rp.Opts(precision=rp.FP32), lanes, epl, gpl, max_requests=16,
                         batch_steps=batch_steps)
