@@ -360,10 +360,63 @@ rac_status launch_group(const std::vector<Job>& jobs, int lpt, const rac_solver_
     return RAC_OK;
 }
 
+using ClassKey = std::tuple<int, int, int>;  // lanes per trajectory, edge slots, gene slots
+
+// Merge launch classes: a class moves into a larger shape of the same lane
+// count and factor form (results stay bit-identical) when the work its padded
+// slots add, trajectories x the cost difference per step, is below what one
+// more launch wastes while it drains, taken as half a residency of the
+// target's trajectories (4096 waves of 64 / lanes each) at the target's cost.
+// Smallest classes first, into the target that adds least, until none moves.
+void merge_classes(std::map<ClassKey, std::vector<Job>>& groups, int precision) {
+    constexpr double kResidentWaves = 4096.0;
+    auto traj_of = [](const std::vector<Job>& js) {
+        double n = 0;
+        for (const Job& j : js) n += (double)j.params.n_sets * j.n_ic;
+        return n;
+    };
+    for (bool moved = true; moved && groups.size() > 1;) {
+        moved = false;
+        std::vector<std::pair<double, ClassKey>> by_work;
+        for (auto& kv : groups) {
+            const auto& [l, e, g] = kv.first;
+            by_work.push_back({traj_of(kv.second) * shape_cost(l, Shape{e, g}, precision), kv.first});
+        }
+        std::sort(by_work.begin(), by_work.end());
+        for (const auto& bw : by_work) {
+            const auto& [l, e, g] = bw.second;
+            const double n = traj_of(groups[bw.second]);
+            const double c_src = shape_cost(l, Shape{e, g}, precision);
+            const ClassKey* best = nullptr;
+            double best_add = 0;
+            for (auto& kv : groups) {
+                const auto& [l2, e2, g2] = kv.first;
+                if (kv.first == bw.second || l2 != l || e2 < e || g2 < g ||
+                    rac_factor_form(precision, e2) != rac_factor_form(precision, e))
+                    continue;
+                const double c_dst = shape_cost(l, Shape{e2, g2}, precision);
+                const double add = n * (c_dst - c_src);
+                const double drain = 0.5 * kResidentWaves * (kWave / l) * c_dst;
+                if (add <= drain && (best == nullptr || add < best_add)) {
+                    best = &kv.first;
+                    best_add = add;
+                }
+            }
+            if (best) {
+                std::vector<Job>& dst = groups[*best];
+                for (Job& j : groups[bw.second]) dst.push_back(j);
+                groups.erase(bw.second);
+                moved = true;
+                break;
+            }
+        }
+    }
+}
+
 rac_status run_jobs(std::vector<Job>& jobs, const rac_solver_opts* o, bool ts,
                     const double* host_t_out, int32_t n_t, void* stream) {
     // Group networks by (lane count, kernel shape): one persistent launch each.
-    std::map<std::tuple<int, int, int>, std::vector<Job>> groups;
+    std::map<ClassKey, std::vector<Job>> groups;
     for (const Job& j : jobs) {
         if (j.params.n_sets == 0) continue;
         const int lpt = j.lanes > 0 ? j.lanes : pick_lanes(j.topo, o);
@@ -375,6 +428,7 @@ rac_status run_jobs(std::vector<Job>& jobs, const rac_solver_opts* o, bool ts,
         const Shape s = pick_shape(std::max(lp->epl, 1), lp->gpl, o->precision);
         groups[std::make_tuple(lpt, s.epl, s.gpl)].push_back(j);
     }
+    merge_classes(groups, o->precision);
     hipStream_t main = (hipStream_t)stream;
     if (groups.size() <= 1) {
         for (auto& kv : groups) {
