@@ -60,3 +60,39 @@ def test_noalloc_needs_a_prepared_lane_plan():
     rp.steady_states_noalloc(T, dp, rp.Opts(precision=rp.FP32), out)
     torch.cuda.synchronize()
     assert int((out.status < 0).sum()) == 0
+
+
+def test_noalloc_replays_from_a_hip_graph():
+    # A caller under graph capture: the call recorded once into a HIP graph
+    # (torch's capture on its own stream) and replayed three times, with eager
+    # solves and synchronisations between the replays; every replay must
+    # equal the eager call bit for bit (the scratch counters are cleared by a
+    # kernel inside the graph, not by a memset node).
+    T = rp.Topology.from_inputs(inputs.erdos_renyi(10, 25, 1002))
+    opts = rp.Opts(precision=rp.FP32, ss_rtol=1e-5)
+    dp = rp.sample_params(T, 777, 2000, 10).to_device()
+    print("[gpu] noalloc under graph capture", flush=True)
+    ref = rp.steady_states(T, dp, opts)  # also puts the lane plan on the device
+    torch.cuda.synchronize()
+    out = _filled(20000, T.n_genes, rp.FP32)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        rp.steady_states_noalloc(T, dp, opts, out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    _same(ref, out)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rp.steady_states_noalloc(T, dp, opts, out)
+    other = rp.sample_params(T, 778, 500, 4).to_device()
+    for rep in range(3):
+        fresh = _filled(20000, T.n_genes, rp.FP32)
+        for f in ("x", "t_final", "status", "n_acc", "n_rej"):
+            getattr(out, f).copy_(getattr(fresh, f))
+        eager = rp.steady_states(T, other, opts)
+        torch.cuda.synchronize()
+        assert int((eager.status < 0).sum()) == 0
+        g.replay()
+        torch.cuda.synchronize()
+        _same(ref, out)
