@@ -468,6 +468,10 @@ rac_status rac_state_counts(const uint64_t* dev_codes, int64_t n_rows, int64_t c
  * bit i % 64 of word i / 64 (N <= 256).
  *  SYNC: every gene updates at once; a trajectory stops at the first state
  *   that maps to itself (steps = updates done) or after max_steps updates.
+ *   A trajectory that revisits a state is periodic; the library then steps
+ *   only the remainder of the updates left modulo the period, so its final
+ *   state, steps and status are those of max_steps updates (Brent's cycle
+ *   detection; dev_evals counts the updates actually done).
  *  ASYNC: one gene per update, cycled from `order` (host array of order_len
  *   gene indices) or chosen at random: update u of trajectory t takes the
  *   low (u even) or high (u odd) 32-bit half h of word (u % 8) / 2 of Philox
@@ -490,6 +494,9 @@ typedef struct {
     uint64_t seed;          /* random gene choices and random initial states */
     const int32_t* order;   /* asynchronous update order (host), or NULL */
     int32_t order_len;
+    unsigned long long* dev_evals; /* optional device counter, or NULL: the gene
+                               evaluations the call performs are added to it
+                               (stream-ordered; the caller zeroes it) */
 } rac_ising_opts;
 
 void rac_default_ising_opts(rac_ising_opts* o);

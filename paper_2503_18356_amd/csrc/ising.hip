@@ -46,6 +46,7 @@ struct IsingArgs {
     uint64_t* final_state;  // [n_traj][W]
     int32_t* steps;
     int8_t* status;
+    unsigned long long* evals;  // optional: gene evaluations performed, summed
     int64_t n_traj;
     uint64_t seed;
     int32_t N, low, max_steps, check_every, order_len, async;
@@ -90,9 +91,11 @@ __global__ __launch_bounds__(kIsingBlock) void ising_kernel(IsingArgs a) {
         for (int w = 0; w < W; ++w) eq = eq && x[w] == y[w];
         return eq;
     };
+    uint64_t lane_evals = 0;  // gene evaluations this lane performed
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < a.n_traj;
          t += (int64_t)gridDim.x * blockDim.x) {
         uint64_t s[W], nxt[W];
+        uint64_t evals = 0;
         if (a.init) {
 #pragma unroll
             for (int w = 0; w < W; ++w) s[w] = a.init[t * W + w];
@@ -109,8 +112,20 @@ __global__ __launch_bounds__(kIsingBlock) void ising_kernel(IsingArgs a) {
         }
         int st = 1, steps = a.max_steps;
         if (!a.async) {
+            // The map is deterministic, so a state seen before means the
+            // trajectory is periodic from there on: its state after
+            // max_steps updates is reached by stepping only the remainder
+            // of the updates left modulo the period.  States are compared
+            // with a checkpoint taken after 1, 2, 4, 8, ... updates, which
+            // finds a cycle of period p after a transient of length m
+            // within 2 max(m, p) + p updates (Brent's cycle detection).
+            uint64_t ref[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) ref[w] = s[w];
+            int ref_at = 0, save_at = 1;
             for (int step = 0; step <= a.max_steps; ++step) {
                 sync_map(s, nxt);
+                ++evals;
                 if (same(nxt, s)) {
                     st = 0;
                     steps = step;
@@ -119,13 +134,31 @@ __global__ __launch_bounds__(kIsingBlock) void ising_kernel(IsingArgs a) {
                 if (step == a.max_steps) break;
 #pragma unroll
                 for (int w = 0; w < W; ++w) s[w] = nxt[w];
+                const int done = step + 1;  // updates applied to s
+                if (same(s, ref)) {
+                    for (int r = (a.max_steps - done) % (done - ref_at); r > 0; --r) {
+                        sync_map(s, nxt);
+                        ++evals;
+#pragma unroll
+                        for (int w = 0; w < W; ++w) s[w] = nxt[w];
+                    }
+                    break;
+                }
+                if (done == save_at) {
+#pragma unroll
+                    for (int w = 0; w < W; ++w) ref[w] = s[w];
+                    ref_at = done;
+                    save_at = done < (1 << 29) ? 2 * done : done;
+                }
             }
+            evals *= N;
         } else {
             const int every = a.check_every > 0 ? a.check_every : N;
             uint64_t blk[4] = {0, 0, 0, 0};
             for (int u = 0; u <= a.max_steps; ++u) {
                 if (u % every == 0) {
                     sync_map(s, nxt);
+                    evals += N;
                     if (same(nxt, s)) {
                         st = 0;
                         steps = u;
@@ -151,6 +184,7 @@ __global__ __launch_bounds__(kIsingBlock) void ising_kernel(IsingArgs a) {
                     i = (int)((h * (uint64_t)N) >> 32);
                 }
                 const uint64_t b = next_bit(s, i);
+                ++evals;
                 s[i >> 6] = (s[i >> 6] & ~(1ull << (i & 63))) | (b << (i & 63));
             }
         }
@@ -158,6 +192,12 @@ __global__ __launch_bounds__(kIsingBlock) void ising_kernel(IsingArgs a) {
         for (int w = 0; w < W; ++w) a.final_state[t * W + w] = s[w];
         if (a.steps) a.steps[t] = steps;
         if (a.status) a.status[t] = (int8_t)st;
+        lane_evals += evals;
+    }
+    if (a.evals) {
+        // One atomic per wave: the wave's sum gathered by shuffles.
+        for (int off = 32; off > 0; off >>= 1) lane_evals += __shfl_xor(lane_evals, off);
+        if ((threadIdx.x & 63) == 0) atomicAdd(a.evals, (unsigned long long)lane_evals);
     }
 }
 
@@ -176,6 +216,7 @@ void rac_default_ising_opts(rac_ising_opts* o) {
     o->seed = 0;
     o->order = nullptr;
     o->order_len = 0;
+    o->dev_evals = nullptr;
 }
 
 rac_status rac_ising(const rac_topology* topo, const rac_ising_opts* o, int64_t n_traj, const uint64_t* dev_init,
@@ -224,6 +265,7 @@ rac_status rac_ising(const rac_topology* topo, const rac_ising_opts* o, int64_t 
     a.final_state = dev_final;
     a.steps = dev_steps;
     a.status = dev_status;
+    a.evals = o->dev_evals;
     a.n_traj = n_traj;
     a.seed = o->seed;
     a.N = N;

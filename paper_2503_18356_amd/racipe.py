@@ -61,7 +61,7 @@ class _Opts(C.Structure):
 class _IsingOpts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("low", C.c_int32), ("max_steps", C.c_int32),
                 ("check_every", C.c_int32), ("seed", C.c_uint64), ("order", C.c_void_p),
-                ("order_len", C.c_int32)]
+                ("order_len", C.c_int32), ("dev_evals", C.c_void_p)]
 
 
 class _Info(C.Structure):
@@ -668,9 +668,12 @@ ISING_SYNC, ISING_ASYNC = 0, 1
 
 
 def ising(topo: Topology, n_traj: int, mode: int = ISING_SYNC, low: int = 0, max_steps: int = 1000,
-          seed: int = 0, init=None, order=None, check_every: int = 0, device="cuda", stream=None):
+          seed: int = 0, init=None, order=None, check_every: int = 0, device="cuda", stream=None,
+          evals=None):
     """(final int64[n_traj][W], steps int32[n_traj], status int8[n_traj]);
-    init: int64[n_traj][W] device tensor or None for seeded random states."""
+    init: int64[n_traj][W] device tensor or None for seeded random states;
+    evals: optional one-element int64 device tensor that the gene
+    evaluations performed are added to."""
     import torch
     W = (topo.n_genes + 63) // 64
     fin = torch.empty((n_traj, W), dtype=torch.int64, device=device)
@@ -684,6 +687,8 @@ def ising(topo: Topology, n_traj: int, mode: int = ISING_SYNC, low: int = 0, max
     if order is not None:
         ordr = np.ascontiguousarray(order, np.int32)
         o.order, o.order_len = ordr.ctypes.data, ordr.size
+    if evals is not None:
+        o.dev_evals = evals.data_ptr()
     _check(lib().rac_ising(topo.handle, C.byref(o), n_traj, _ptr(init), fin.data_ptr(), steps.data_ptr(),
                            status.data_ptr(), _stream_ptr(stream)))
     return fin, steps, status

@@ -115,3 +115,35 @@ def test_sync_wide_fan_in(n_genes):
     init = rng.random((3000, n_genes)) < 0.5
     for low in (0, -1):
         _check(topo, 3000, "sync", low, 500, 9, 60, init=init, extra_ids=[0, 2999])
+
+
+@pytest.mark.parametrize("low", [0, -1])
+def test_sync_cycles_at_many_step_limits(low):
+    # Periodic synchronous trajectories stop stepping once their cycle is
+    # found and step only the remainder modulo the period: the final state,
+    # count and status must equal the oracle's plain stepping for any limit,
+    # including limits shorter than the detection and every residue.
+    topo = inputs.dense_core(1004)
+    for max_steps in (0, 1, 2, 3, 7, 64, 65, 127, 1000, 1001):
+        _check(topo, 4000, "sync", low, max_steps, 31 + max_steps, 60)
+    topo = inputs.erdos_renyi(40, 100, 23)
+    for max_steps in (5, 333, 2048):
+        _check(topo, 2000, "sync", low, max_steps, 41 + max_steps, 40)
+
+
+def test_sync_evaluation_counter():
+    # Toggle switch with off = -1: (0,0) and (1,1) alternate with period 2,
+    # found after four updates (checkpoints after 1 and 2 updates); (0,1) and
+    # (1,0) are fixed at once.  Performed gene evaluations: 4 x 2 + 1 x 2 +
+    # 1 x 2 + 4 x 2 = 20, though the results stand for 50 updates of the
+    # periodic pair.
+    T = rp.Topology.from_inputs(inputs.toggle_switch())
+    init = np.array([[0, 0], [0, 1], [1, 0], [1, 1]], bool)
+    dev_init = torch.from_numpy(oi.pack(init).view(np.int64)).cuda()
+    ev = torch.zeros(1, dtype=torch.int64, device="cuda")
+    fin, steps, status = rp.ising(T, 4, rp.ISING_SYNC, -1, 50, 0, init=dev_init, evals=ev)
+    torch.cuda.synchronize()
+    assert int(ev.item()) == 20
+    got = oi.unpack(fin.cpu().numpy().view(np.uint64), 2)
+    assert np.array_equal(got, init)  # even step count: back where they started
+    assert steps.cpu().tolist() == [50, 0, 0, 50] and status.cpu().tolist() == [1, 0, 0, 1]
