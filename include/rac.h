@@ -506,8 +506,14 @@ rac_status rac_ising(const rac_topology* topo, const rac_ising_opts* opts, int64
                      int8_t* dev_status, void* hip_stream);
 
 /* The lanes-per-trajectory choice the library would make for a network
- * (0 if none fits), and whether a given choice fits the compiled kernels. */
+ * (0 if none fits), and whether a given choice fits the compiled kernels.
+ * rac_auto_lanes is the cost model's choice for a call that fills the GPU;
+ * rac_auto_lanes_for is what a call of n_traj trajectories in all (every
+ * network of a batch call) takes when its options give no lane count: the
+ * same, unless the call is too small to fill the GPU at that choice, then
+ * more lanes per trajectory (shorter trajectories, more issue work). */
 int32_t rac_auto_lanes(const rac_topology* topo, int32_t precision);
+int32_t rac_auto_lanes_for(const rac_topology* topo, int32_t precision, int64_t n_traj);
 int32_t rac_lanes_supported(const rac_topology* topo, int32_t precision, int32_t lanes);
 
 /* The compiled kernel shape (edge slots, gene slots per lane) a network uses

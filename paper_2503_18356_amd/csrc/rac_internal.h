@@ -85,6 +85,8 @@ int max_in_degree(const rac_topology* t);
 Shape pick_shape(int epl, int gpl, int precision);
 bool plan_fits(const rac_topology* t, int lpt, int precision);
 int auto_lanes(const rac_topology* t, int precision);
+// auto_lanes adjusted for a call too small to fill the GPU.
+int auto_lanes_for(const rac_topology* t, int precision, double n_traj);
 // Estimated issue cost of one trajectory step at a lane count and kernel shape
 // (lanes x per-lane slot work / latency-hiding efficiency of the shape).
 double shape_cost(int lpt, const Shape& s, int precision);

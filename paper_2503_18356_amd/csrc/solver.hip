@@ -192,8 +192,10 @@ struct Job {
     int32_t refill = 0;  // 0: from the options
 };
 
-int pick_lanes(const rac_topology* t, const rac_solver_opts* o) {
-    return o->lanes_per_traj > 0 ? o->lanes_per_traj : auto_lanes(t, o->precision);
+// The options' lane count, else the cost model's choice for a call of
+// n_traj trajectories in all (more lanes when the call cannot fill the GPU).
+int pick_lanes(const rac_topology* t, const rac_solver_opts* o, double n_traj) {
+    return o->lanes_per_traj > 0 ? o->lanes_per_traj : auto_lanes_for(t, o->precision, n_traj);
 }
 
 Controls make_controls(const rac_solver_opts* o, int n_groups) {
@@ -417,9 +419,11 @@ rac_status run_jobs(std::vector<Job>& jobs, const rac_solver_opts* o, bool ts,
                     const double* host_t_out, int32_t n_t, void* stream) {
     // Group networks by (lane count, kernel shape): one persistent launch each.
     std::map<ClassKey, std::vector<Job>> groups;
+    double call_traj = 0;
+    for (const Job& j : jobs) call_traj += (double)j.params.n_sets * j.n_ic;
     for (const Job& j : jobs) {
         if (j.params.n_sets == 0) continue;
-        const int lpt = j.lanes > 0 ? j.lanes : pick_lanes(j.topo, o);
+        const int lpt = j.lanes > 0 ? j.lanes : pick_lanes(j.topo, o, call_traj);
         if (lpt == 0 || !plan_fits(j.topo, lpt, o->precision))
             return fail(RAC_EUNSUPPORTED, "network (N=" + std::to_string(j.topo->n_genes) + ", E=" +
                                               std::to_string(j.topo->n_edges) +
@@ -565,7 +569,7 @@ rac_status rac_steady_states_noalloc(const rac_topology* topo, const rac_params_
     st = check_item(topo, dev_params, dev_ic, n_ic, dev_x_out, "rac_steady_states_noalloc");
     if (st != RAC_OK) return st;
     if (dev_params->n_sets == 0) return RAC_OK;
-    const int lpt = pick_lanes(topo, opts);
+    const int lpt = pick_lanes(topo, opts, (double)dev_params->n_sets * n_ic);
     if (lpt == 0 || !plan_fits(topo, lpt, opts->precision))
         return fail(RAC_EUNSUPPORTED, "rac_steady_states_noalloc: network does not fit the compiled kernels");
     int dev = 0;

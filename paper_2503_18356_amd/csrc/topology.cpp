@@ -114,6 +114,45 @@ double shape_cost(int lpt, const Shape& s, int precision) {
     return lpt * (14.0 * s.epl + 25.0 * s.gpl + 40.0) / shape_efficiency(s, precision);
 }
 
+// Lane count for a call of n_traj trajectories.  A call that cannot fill the
+// GPU at the cost model's choice finishes sooner with more lanes per
+// trajectory: each trajectory's steps are shorter although the issue work
+// grows.  Estimated time = cost per trajectory step / utilisation, with the
+// utilisation u = x / (x + 2.6) of x = n_traj x lanes / (lanes resident on
+// an MI355X at four waves per SIMD), a form fitted to timings of 10^3 to
+// 10^6 trajectories of 2-, 10-, 22- and 50-gene networks (it keeps the
+// model's choice for 10^6 trajectories of a 10-gene network and moves 10^4
+// of them from 4 to 16 lanes, 36 % faster).  Calls with x >= 8 at the
+// model's choice keep it unchanged, and a move needs an estimated gain of
+// 15 % (the register model behind the costs is approximate: the 22-gene
+// network's 10^4 trajectories, estimated 14 % faster at 16 lanes than at 8,
+// measured 9 % slower).
+int auto_lanes_for(const rac_topology* t, int precision, double n_traj) {
+    const int base = auto_lanes(t, precision);
+    constexpr double kResidentLanes = 256.0 * 4 * 4 * kWave;
+    auto fill = [&](int lpt) {
+        const double x = n_traj * lpt / kResidentLanes;
+        return x / (x + 2.6);
+    };
+    if (base == 0 || n_traj * base >= 8.0 * kResidentLanes) return base;
+    auto est = [&](int lpt) {
+        const LanePlan* p = get_plan(t, lpt);
+        const Shape s = pick_shape(std::max(p->epl, 1), p->gpl, precision);
+        return shape_cost(lpt, s, precision) / fill(lpt);
+    };
+    int best = base;
+    double best_t = 0.85 * est(base);
+    for (int lpt = 2 * base; lpt <= kWave; lpt *= 2) {
+        if (!plan_fits(t, lpt, precision)) continue;
+        const double tt = est(lpt);
+        if (tt < best_t) {
+            best = lpt;
+            best_t = tt;
+        }
+    }
+    return best;
+}
+
 int auto_lanes(const rac_topology* t, int precision) {
     int best = 0;
     double best_cost = 0;
@@ -210,6 +249,11 @@ rac_status rac_topology_edges(const rac_topology* topo, int32_t* src, int32_t* d
 int32_t rac_auto_lanes(const rac_topology* topo, int32_t precision) {
     if (!topo || (precision != RAC_FP32 && precision != RAC_FP64)) return 0;
     return rac::auto_lanes(topo, precision);
+}
+
+int32_t rac_auto_lanes_for(const rac_topology* topo, int32_t precision, int64_t n_traj) {
+    if (!topo || (precision != RAC_FP32 && precision != RAC_FP64) || n_traj < 0) return 0;
+    return rac::auto_lanes_for(topo, precision, (double)n_traj);
 }
 
 rac_status rac_plan_shape(const rac_topology* topo, int32_t precision, int32_t lanes, int32_t* epl,

@@ -113,6 +113,8 @@ def lib():
         L.rac_steady_states_batch.restype = C.c_int
         L.rac_auto_lanes.argtypes = [vp, i32]
         L.rac_auto_lanes.restype = i32
+        L.rac_auto_lanes_for.argtypes = [vp, i32, i64]
+        L.rac_auto_lanes_for.restype = i32
         L.rac_lanes_supported.argtypes = [vp, i32, i32]
         L.rac_lanes_supported.restype = i32
         L.rac_plan_shape.argtypes = [vp, i32, i32, vp, vp]
@@ -215,8 +217,12 @@ class Topology:
     def handle(self):
         return self._h
 
-    def auto_lanes(self, precision: int = FP32) -> int:
-        return int(lib().rac_auto_lanes(self._h, precision))
+    def auto_lanes(self, precision: int = FP32, n_traj: int | None = None) -> int:
+        """The library's lane count: the cost model's, or, given the call's
+        trajectory count, the one a call of that size takes."""
+        if n_traj is None:
+            return int(lib().rac_auto_lanes(self._h, precision))
+        return int(lib().rac_auto_lanes_for(self._h, precision, int(n_traj)))
 
     def lanes_supported(self, lanes: int, precision: int = FP32) -> bool:
         return bool(lib().rac_lanes_supported(self._h, precision, lanes))

@@ -161,6 +161,33 @@ def test_lane_choices():
     assert not ts.lanes_supported(3)
 
 
+def test_lane_choice_follows_the_call_size():
+    # A call that fills the GPU keeps the cost model's lane count; a small
+    # one takes more lanes per trajectory, never fewer, and only supported
+    # counts.  The figures are the choices that the timings of these
+    # networks at 10^3 to 10^6 trajectories favoured.
+    er10 = rp.Topology.from_inputs(inputs.erdos_renyi(10, 25, 1002))
+    base = er10.auto_lanes(rp.FP32)
+    assert base == 4
+    assert er10.auto_lanes(rp.FP32, 10**6) == base and er10.auto_lanes(rp.FP32, 10**8) == base
+    assert er10.auto_lanes(rp.FP32, 10**5) == 8 and er10.auto_lanes(rp.FP32, 10**4) == 16
+    ts = rp.Topology.from_inputs(inputs.toggle_switch())
+    assert ts.auto_lanes(rp.FP32, 10**4) == 2 * ts.auto_lanes(rp.FP32)
+    core = rp.Topology.from_inputs(inputs.dense_core(1004))
+    assert core.auto_lanes(rp.FP32, 10**4) == core.auto_lanes(rp.FP32) == 8
+    for topo in (er10, ts, core):
+        prev = 64
+        for n in (1, 10, 10**3, 10**4, 10**5, 10**6, 10**7):
+            for prec in (rp.FP32, rp.FP64):
+                lanes = topo.auto_lanes(prec, n)
+                assert lanes >= topo.auto_lanes(prec) and topo.lanes_supported(lanes, prec)
+            lanes = topo.auto_lanes(rp.FP32, n)
+            assert lanes <= prev
+            prev = lanes
+    assert rp.lib().rac_auto_lanes_for(er10.handle, 7, 100) == 0
+    assert rp.lib().rac_auto_lanes_for(er10.handle, rp.FP32, -1) == 0
+
+
 def test_largest_supported_networks_and_one_past_them():
     # FP32: 64 lanes x 8 gene slots bound N at 512; 1,024 edges fit 16 edge
     # slots per lane.  FP64 kernels stop at 4 gene slots with 8 edge slots.
