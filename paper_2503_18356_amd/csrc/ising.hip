@@ -91,11 +91,19 @@ __global__ __launch_bounds__(kIsingBlock) void ising_kernel(IsingArgs a) {
         for (int w = 0; w < W; ++w) eq = eq && x[w] == y[w];
         return eq;
     };
+    // Persistent lanes: a lane takes trajectories t, t + stride, ... and
+    // starts the next as soon as one ends, so a wave no longer waits for
+    // the slowest of its 64 trajectories before any lane moves on.
     uint64_t lane_evals = 0;  // gene evaluations this lane performed
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < a.n_traj;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        uint64_t s[W], nxt[W];
-        uint64_t evals = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    uint64_t s[W], nxt[W], ref[W];
+    uint64_t blk[4] = {0, 0, 0, 0};
+    int st = 1, steps = 0, step = 0, ref_at = 0, save_at = 1, left = -1, u = 0;
+    bool have = false, wait = false;
+    auto start = [&]() {
+        have = t < a.n_traj;
+        if (!have) return;
         if (a.init) {
 #pragma unroll
             for (int w = 0; w < W; ++w) s[w] = a.init[t * W + w];
@@ -105,67 +113,97 @@ __global__ __launch_bounds__(kIsingBlock) void ising_kernel(IsingArgs a) {
 #pragma unroll
             for (int w = 0; w < W; ++w) s[w] = 0;
             for (int i = 0; i < N; i += 4) {
-                uint64_t blk[4] = {(uint64_t)t, (uint64_t)(i >> 2), 9, 0};
-                philox(blk, a.seed, 0);
-                for (int j = 0; j < 4 && i + j < N; ++j) s[(i + j) >> 6] |= (blk[j] >> 63) << ((i + j) & 63);
+                uint64_t b[4] = {(uint64_t)t, (uint64_t)(i >> 2), 9, 0};
+                philox(b, a.seed, 0);
+                for (int j = 0; j < 4 && i + j < N; ++j) s[(i + j) >> 6] |= (b[j] >> 63) << ((i + j) & 63);
             }
         }
-        int st = 1, steps = a.max_steps;
-        if (!a.async) {
-            // The map is deterministic, so a state seen before means the
-            // trajectory is periodic from there on: its state after
-            // max_steps updates is reached by stepping only the remainder
-            // of the updates left modulo the period.  States are compared
-            // with a checkpoint taken after 1, 2, 4, 8, ... updates, which
-            // finds a cycle of period p after a transient of length m
-            // within 2 max(m, p) + p updates (Brent's cycle detection).
-            uint64_t ref[W];
+        st = 1;
+        steps = a.max_steps;
+        step = 0;
+        u = 0;
+        left = -1;
 #pragma unroll
-            for (int w = 0; w < W; ++w) ref[w] = s[w];
-            int ref_at = 0, save_at = 1;
-            for (int step = 0; step <= a.max_steps; ++step) {
-                sync_map(s, nxt);
-                ++evals;
-                if (same(nxt, s)) {
-                    st = 0;
-                    steps = step;
-                    break;
-                }
-                if (step == a.max_steps) break;
+        for (int w = 0; w < W; ++w) ref[w] = s[w];
+        ref_at = 0;
+        save_at = 1;
+    };
+    auto finish = [&]() {
+#pragma unroll
+        for (int w = 0; w < W; ++w) a.final_state[t * W + w] = s[w];
+        if (a.steps) a.steps[t] = steps;
+        if (a.status) a.status[t] = (int8_t)st;
+        t += stride;
+        start();
+    };
+    start();
+    if (!a.async) {
+        // One map evaluation per lane per iteration.  The map is
+        // deterministic, so a state seen before means the trajectory is
+        // periodic from there on: its state after max_steps updates is
+        // reached by stepping only the remainder (`left`) of the updates
+        // left modulo the period.  States are compared with a checkpoint
+        // taken after 1, 2, 4, 8, ... updates, which finds a cycle of period
+        // p after a transient of length m within 2 max(m, p) + p updates
+        // (Brent's cycle detection).
+        while (__ballot(have) != 0) {
+            if (!have) continue;
+            sync_map(s, nxt);
+            lane_evals += N;
+            if (left > 0) {
 #pragma unroll
                 for (int w = 0; w < W; ++w) s[w] = nxt[w];
-                const int done = step + 1;  // updates applied to s
-                if (same(s, ref)) {
-                    for (int r = (a.max_steps - done) % (done - ref_at); r > 0; --r) {
-                        sync_map(s, nxt);
-                        ++evals;
+                if (--left == 0) finish();
+            } else if (same(nxt, s)) {
+                st = 0;
+                steps = step;
+                finish();
+            } else if (step == a.max_steps) {
+                finish();
+            } else {
 #pragma unroll
-                        for (int w = 0; w < W; ++w) s[w] = nxt[w];
-                    }
-                    break;
-                }
-                if (done == save_at) {
+                for (int w = 0; w < W; ++w) s[w] = nxt[w];
+                const int done = ++step;  // updates applied to s
+                if (same(s, ref)) {
+                    left = (a.max_steps - done) % (done - ref_at);
+                    if (left == 0) finish();
+                } else if (done == save_at) {
 #pragma unroll
                     for (int w = 0; w < W; ++w) ref[w] = s[w];
                     ref_at = done;
                     save_at = done < (1 << 29) ? 2 * done : done;
                 }
             }
-            evals *= N;
-        } else {
-            const int every = a.check_every > 0 ? a.check_every : N;
-            uint64_t blk[4] = {0, 0, 0, 0};
-            for (int u = 0; u <= a.max_steps; ++u) {
+        }
+    } else {
+        // Rounds of `every` updates.  Every lane's fixed-point tests fall on
+        // a round start (u % every == 0), so the wave runs the test's full
+        // map evaluation once per round for all lanes; a trajectory started
+        // in a round's test phase waits for the next round's test.
+        const int every = a.check_every > 0 ? a.check_every : N;
+        while (__ballot(have) != 0) {
+            if (have) {
                 if (u % every == 0) {
                     sync_map(s, nxt);
-                    evals += N;
+                    lane_evals += N;
                     if (same(nxt, s)) {
                         st = 0;
                         steps = u;
-                        break;
+                        finish();
+                        wait = true;
+                    } else if (u == a.max_steps) {
+                        finish();
+                        wait = true;
                     }
+                } else if (u == a.max_steps) {
+                    finish();
+                    wait = true;
                 }
-                if (u == a.max_steps) break;
+            }
+            for (int k = 0; k < every; ++k) {
+                const bool busy = have && !wait && u < a.max_steps;
+                if (__ballot(busy) == 0) break;  // bounded by the updates left, not by `every`
+                if (!busy) continue;
                 int i;
                 if (a.order) {
                     i = a.order[u % a.order_len];
@@ -184,15 +222,12 @@ __global__ __launch_bounds__(kIsingBlock) void ising_kernel(IsingArgs a) {
                     i = (int)((h * (uint64_t)N) >> 32);
                 }
                 const uint64_t b = next_bit(s, i);
-                ++evals;
+                ++lane_evals;
                 s[i >> 6] = (s[i >> 6] & ~(1ull << (i & 63))) | (b << (i & 63));
+                ++u;
             }
+            wait = false;
         }
-#pragma unroll
-        for (int w = 0; w < W; ++w) a.final_state[t * W + w] = s[w];
-        if (a.steps) a.steps[t] = steps;
-        if (a.status) a.status[t] = (int8_t)st;
-        lane_evals += evals;
     }
     if (a.evals) {
         // One atomic per wave: the wave's sum gathered by shuffles.
@@ -238,6 +273,20 @@ rac_status rac_ising(const rac_topology* topo, const rac_ising_opts* o, int64_t 
     if (n_traj == 0) return RAC_OK;
     const int W = (N + 63) / 64;
     hipStream_t s = (hipStream_t)hip_stream;
+    // Grid: synchronous calls take a lane per trajectory up to 256 blocks per
+    // CU; asynchronous ones at most 16 blocks (64 waves) per CU, past which
+    // each lane works through several trajectories and refills as each ends.
+    // Refill pays off where trajectories are long and uneven (asynchronous,
+    // 10^7 states: 349 against 457 ms) and costs where they are short
+    // (synchronous, 10^7 states: 20.5 against 13.3 ms: a random initial
+    // state takes six Philox blocks, which the whole wave waits for whenever
+    // one of its lanes starts a trajectory).
+    int dev = 0, n_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1)
+        return fail(RAC_EDEVICE, "rac_ising: device query failed");
+    const int per_cu = o->mode == RAC_ISING_ASYNC ? 16 : 256;
+    const int blocks = (int)std::min<int64_t>((n_traj + kIsingBlock - 1) / kIsingBlock, (int64_t)n_cu * per_cu);
     // Regulator masks per gene, uploaded stream-ordered; a host callback frees
     // the staging copy once the copy has run.
     const size_t n_mask = (size_t)N * 2 * W;
@@ -274,7 +323,7 @@ rac_status rac_ising(const rac_topology* topo, const rac_ising_opts* o, int64_t 
     a.check_every = o->check_every;
     a.order_len = o->order_len;
     a.async = o->mode == RAC_ISING_ASYNC;
-    const int blocks = (int)std::min<int64_t>((n_traj + kIsingBlock - 1) / kIsingBlock, 65536);
+
     if (W == 1)
         hipLaunchKernelGGL(ising_kernel<1>, dim3(blocks), dim3(kIsingBlock), 0, s, a);
     else if (W == 2)

@@ -147,3 +147,26 @@ def test_sync_evaluation_counter():
     got = oi.unpack(fin.cpu().numpy().view(np.uint64), 2)
     assert np.array_equal(got, init)  # even step count: back where they started
     assert steps.cpu().tolist() == [50, 0, 0, 50] and status.cpu().tolist() == [1, 0, 0, 1]
+
+
+def test_async_test_interval_beyond_the_step_limit():
+    # A fixed-point test interval far above max_steps: one test at the start,
+    # then plain updates to the limit (the round loop ends with the updates
+    # left, not after `check_every` empty passes).
+    _check(inputs.dense_core(1004), 3000, "async", -1, 60, 13, 80, check_every=1_000_000)
+    _check(inputs.dense_core(1004), 3000, "async", 0, 61, 14, 80, check_every=7)
+
+
+@pytest.mark.parametrize("mode", ["sync", "async"])
+def test_lanes_that_take_several_trajectories(mode):
+    # Past a grid's worth of lanes (synchronous: 256 blocks of 256 per CU,
+    # 16.8 M on 256 CUs; asynchronous: 16 per CU, 1.05 M) a lane starts its
+    # next trajectory when one ends.  Trajectories of the second pass, and
+    # the first-pass ones of the same lanes, against the oracle.
+    topo = inputs.dense_core(1004)
+    lanes = (256 if mode == "sync" else 16) * 256 * 256
+    n = lanes + 3000
+    tail = np.arange(lanes, n, 97)
+    extra = np.concatenate([tail, tail - lanes, [0, n - 1]])
+    max_steps = 1000 if mode == "sync" else 3000
+    _check(topo, n, mode, -1, max_steps, 17, 20, extra_ids=extra)
