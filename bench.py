@@ -8,9 +8,10 @@ trajectories in all), Table 1 parameter ranges (GRiNS Sec. 2.1.2), DP5(4)
 with rtol 1e-6, atol 1e-9, t_end 200, steady when |dx_i/dt| <= 1e-6 +
 1e-5 k_i |x_i|.  Parameters and initial conditions are resident in HBM before
 timing starts.  The chosen form is FP32 state with FP64 time / error norm /
-steady test in persistent work-queue launches, with the autotuner's lane
-counts where a whole untimed batch call with them beats the library's lane
-model, else the model's; the plain form is FP64, one launch per network.
+steady test in persistent work-queue launches, with the library's lane
+model and the autotuner's choices switched in class by class where whole
+untimed batch calls get faster; the plain form is FP64, one launch per
+network.
 
 The JSON line reports solves/s of the chosen form, the plain form, the
 credited FP32 FLOP/s of the batch call against the MI355X vector peak, the
@@ -416,9 +417,10 @@ def bench_uneven64(args, torch, rp, flops, inputs):
     o32 = rp.Opts(precision=rp.FP32, lanes_per_traj=args.lanes, refill_min=args.refill_min)
     outs = [rp.alloc_result(p.n_sets * 10, T.n_genes, rp.FP32) for T, p in items]
     fill = lambda: [rp.fill_sentinels(o) for o in outs]
-    # Lane counts and refill batches: the library's cost model (default), or
-    # the autotuner's per-network measurements when one whole batch call with
-    # them beats the model's (decided on untimed calls before the timed ones).
+    # Lane counts and refill batches: the library's cost model (default),
+    # with the autotuner's per-network choices switched in class by class
+    # where whole batch calls get faster (decided on untimed calls before
+    # the timed ones).
     knobs = [(0, 0)] * len(items)
     tune_rec = None
     if not args.no_tune and args.lanes == 0 and args.refill_min == 0:
@@ -438,14 +440,25 @@ def bench_uneven64(args, torch, rp, flops, inputs):
             e1.synchronize()
             return e0.elapsed_time(e1) * 1e-3
         default_knobs = knobs
-        knobs, pick_t = Autotuner.pick_faster(run_knobs, tuned, default_knobs)
+        # Networks grouped by the launch class the lane model gives them,
+        # largest class first; each group switches to its tuned knobs only
+        # if a whole batch call gets faster.
+        n_total = sum(p.n_sets * 10 for _, p in items)
+        cls = {}
+        for i, (T, p) in enumerate(items):
+            lanes = T.auto_lanes(rp.FP32, n_total)
+            cls.setdefault((lanes, T.shape(lanes, rp.FP32)), []).append(i)
+        groups = sorted(cls.values(), key=lambda g: -sum(items[i][1].n_sets for i in g))
+        knobs, refine_log = Autotuner.refine_batch(run_knobs, default_knobs, tuned, groups)
         run_d = lambda: rp.steady_states_batch([(T, p, o) for (T, p), o in zip(items, outs)], o32, stream=stream)
         wall_d, lat_d = timed(run_d, args.steps, stream, torch, before_last=fill)
         tune_rec = {"seconds": t_tune,
                     "sample": "per network bucket, marginal solves/s between 2x and 4x the GPU's resident "
-                              "trajectories, HIP-event timed",
-                    "picked": "tuned" if knobs is tuned else "default",
-                    "pick_ms": {k: v * 1e3 for k, v in pick_t.items()},
+                              "trajectories, HIP-event timed; then per launch class of the lane model, "
+                              "largest first, the tuned knobs kept only where a whole untimed batch call "
+                              "runs more than 1 % faster",
+                    "groups_switched": sum(1 for r in refine_log[1:] if r["kept"]),
+                    "refine": refine_log,
                     "default_value": sum(solved(rp, o) for o in outs) * args.steps / wall_d,
                     "default_ms": float(lat_d.mean()),
                     "choices": [{"N": T.n_genes, "E": T.n_edges, "lanes_default": T.auto_lanes(rp.FP32),

@@ -168,3 +168,31 @@ class Autotuner:
             run(knobs)
             t[name] = min(run(knobs) for _ in range(reps))
         return (tuned if t["tuned"] < t["default"] else default), t
+
+    @staticmethod
+    def refine_batch(run, default, tuned, groups, reps: int = 2, margin: float = 0.01):
+        """Greedy refinement on the whole batch: starting from the default
+        knob list, switch one group of items (e.g. the networks of one
+        launch class of the default plan, largest first) to its tuned
+        knobs, and keep the switch when a whole batch call runs more than
+        `margin` faster than the best so far.  run(knobs) solves the batch
+        once and returns its seconds; each timing is the best of `reps`
+        after one untimed call.  Returns (knobs, log)."""
+        def best_of(knobs):
+            run(knobs)
+            return min(run(knobs) for _ in range(reps))
+        current = list(default)
+        t_best = best_of(current)
+        log = [{"group": None, "ms": t_best * 1e3, "kept": True}]
+        for g in groups:
+            if all(tuned[i] == current[i] for i in g):
+                continue
+            trial = list(current)
+            for i in g:
+                trial[i] = tuned[i]
+            t = best_of(trial)
+            kept = t < t_best * (1.0 - margin)
+            log.append({"group": list(g), "ms": t * 1e3, "kept": kept})
+            if kept:
+                current, t_best = trial, t
+        return current, log
