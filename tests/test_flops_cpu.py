@@ -29,3 +29,30 @@ def test_autotune_bucket_rounds_up():
     t = inputs.erdos_renyi(10, 25, 1002)
     b = bucket(t)
     assert b.startswith("N16_E32_D")
+
+
+def test_refine_batch_keeps_only_switches_that_pay():
+    # refine_batch with a synthetic batch time: switching group A saves 5 %,
+    # group B costs 3 %, group C saves 0.4 % (below the 1 % margin).
+    from paper_2503_18356_amd.autotune import Autotuner
+    default = [(0, 0)] * 6
+    tuned = [(4, 2), (4, 2), (16, 1), (16, 1), (8, 4), (8, 4)]
+    effect = {0: -0.05, 2: 0.03, 4: -0.004}
+    calls = []
+
+    def run(knobs):
+        calls.append(list(knobs))
+        t = 1.0
+        for first, d in effect.items():
+            if knobs[first] != (0, 0):
+                t *= 1.0 + d
+        return t
+
+    knobs, log = Autotuner.refine_batch(run, default, tuned, [[0, 1], [2, 3], [4, 5]])
+    assert knobs == [(4, 2), (4, 2), (0, 0), (0, 0), (0, 0), (0, 0)]
+    assert [r["kept"] for r in log] == [True, True, False, False]
+    # One untimed call and two timed ones per trial: the start and three groups.
+    assert len(calls) == 4 * 3
+    # A group whose tuned knobs equal the current ones is not tried again.
+    knobs2, log2 = Autotuner.refine_batch(run, default, default, [[0, 1]])
+    assert knobs2 == default and len(log2) == 1
