@@ -12,10 +12,14 @@ arrival to the host seeing the request's last trajectory finish.
 
 The scheduler talks to an executor (``GpuExecutor`` here); tests drive it
 with a CPU stand-in to check admission, ordering and accounting.
+``Server`` is the interactive form: ``submit()`` from any thread returns a
+future while a background thread runs the scheduler loop.
 """
 from __future__ import annotations
 
 import collections
+import concurrent.futures
+import threading
 import time
 from dataclasses import dataclass, field
 
@@ -43,6 +47,88 @@ class Request:
     @property
     def latency(self) -> float:
         return self.finished - self.arrival
+
+
+class Server:
+    """Interactive front end of the serving loop: ``submit()`` may be called
+    from any thread, also while other requests are on the GPU, and returns a
+    ``concurrent.futures.Future`` that resolves to the finished ``Request``
+    (``.result`` holds its steady states and per-trajectory info on the
+    device, ``.latency`` its arrival-to-finish time).  A background thread
+    admits requests by HBM footprint and runs the continuous-batching steps;
+    a request that can never fit the budget fails its future with
+    ``MemoryError``.  ``close()`` lets the requests in flight finish and
+    stops the thread."""
+
+    def __init__(self, hbm_budget: int = 64 << 30, opts=None, batch_steps: int = 512, executor=None,
+                 clock=time.perf_counter):
+        self.ex = executor if executor is not None else GpuExecutor(opts=opts, batch_steps=batch_steps)
+        self.sched = Scheduler(self.ex, hbm_budget, clock=clock)
+        self._cv = threading.Condition()
+        self._new: collections.deque[Request] = collections.deque()
+        self._futures: dict[int, concurrent.futures.Future] = {}
+        self._next = 0
+        self._closed = False
+        self._n_done = self._n_rejected = 0
+        self._thread = threading.Thread(target=self._loop, name="racipe-server", daemon=True)
+        self._thread.start()
+
+    def submit(self, topo, seed: int, n_sets: int, n_ic: int) -> concurrent.futures.Future:
+        fut: concurrent.futures.Future = concurrent.futures.Future()
+        with self._cv:
+            if self._closed:
+                raise RuntimeError("server is closed")
+            req = Request(self._next, topo, seed, n_sets, n_ic)
+            self._next += 1
+            self._futures[req.rid] = fut
+            self._new.append(req)
+            self._cv.notify()
+        return fut
+
+    def _settle(self):
+        done, rej = self.sched.done, self.sched.rejected
+        for req in done[self._n_done:]:
+            self._futures.pop(req.rid).set_result(req)
+        for req in rej[self._n_rejected:]:
+            self._futures.pop(req.rid).set_exception(
+                MemoryError(f"request {req.rid} needs {req.nbytes} bytes, over the HBM budget"))
+        self._n_done, self._n_rejected = len(done), len(rej)
+
+    def _loop(self):
+        try:
+            while True:
+                with self._cv:
+                    while not self._new and self.sched.idle() and not self._closed:
+                        self._cv.wait()
+                    if self._closed and not self._new and self.sched.idle():
+                        return
+                    new = list(self._new)
+                    self._new.clear()
+                for req in new:
+                    self.sched.arrive(req)
+                self.sched.admit()
+                if self.sched.running:
+                    self.sched.step()
+                self._settle()
+        except BaseException as e:  # fail every outstanding future, then stop
+            with self._cv:
+                self._closed = True
+                for fut in self._futures.values():
+                    if not fut.done():
+                        fut.set_exception(e)
+                self._futures.clear()
+
+    def close(self, timeout: float | None = None):
+        with self._cv:
+            self._closed = True
+            self._cv.notify()
+        self._thread.join(timeout)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def footprint_bytes(n_genes: int, n_edges: int, n_sets: int, n_ic: int, x_bytes: int = 4) -> int:

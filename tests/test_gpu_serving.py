@@ -315,3 +315,35 @@ def test_full_request_tables_open_new_generations():
         prm = rp.sample_params(T, req.seed, req.n_sets, req.n_ic).to_device()
         ref = _direct(T, prm, req.handle["class"][0])
         assert torch.equal(req.result.x, ref.x), req.rid
+
+
+def test_interactive_server_futures():
+    # The submit -> future front end: requests submitted from two threads
+    # while earlier ones are on the GPU; each future's request equals its own
+    # one-shot solve at the lane count its class used, bit for bit.
+    import concurrent.futures as cf
+    import time as _time
+    from paper_2503_18356_amd import inputs as _inputs
+    from paper_2503_18356_amd.serve import Server
+    rng = np.random.default_rng(23)
+    specs = [_inputs.serving_request(rng, 2, 30, 50, 2000, 1, 5) for _ in range(12)]
+    say("[gpu] interactive server,", len(specs), "requests")
+    with Server(hbm_budget=8 << 30, batch_steps=128) as srv:
+        def feed(part):
+            out = []
+            for i, (topo, P, n_ic) in part:
+                out.append(srv.submit(topo, 900 + i, P, n_ic))
+                _time.sleep(0.003)
+            return out
+        items = list(enumerate(specs))
+        with cf.ThreadPoolExecutor(2) as pool:
+            parts = list(pool.map(feed, (items[0::2], items[1::2])))
+        futs = [f for part in parts for f in part]
+        done = [f.result(timeout=240) for f in futs]
+    assert len({d.rid for d in done}) == len(specs)
+    for req in done:
+        T = req.handle["T"]
+        prm = rp.sample_params(T, req.seed, req.n_sets, req.n_ic).to_device()
+        ref = _direct(T, prm, req.handle["class"][0])
+        assert torch.equal(req.result.x, ref.x), req.rid
+        assert req.latency > 0

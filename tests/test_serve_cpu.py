@@ -2,6 +2,7 @@
 continuous batching and latency accounting, driven by a stand-in executor
 that solves tiny networks with the oracle."""
 import numpy as np
+import pytest
 
 import oracle
 from paper_2503_18356_amd import inputs
@@ -130,3 +131,36 @@ def test_oversized_request_is_rejected_not_blocking():
 def test_footprint_formula():
     # parameters + ICs + states + 17 bytes of info per trajectory
     assert footprint_bytes(2, 2, 10, 3) == 10 * (16 + 16 + 2) + 3 * 8 + 30 * (8 + 17)
+
+
+def test_server_futures_from_several_threads():
+    # The interactive front end: requests submitted from four threads while
+    # others run; every future resolves to its finished request with the
+    # stand-in executor's (oracle) result, and a request that can never fit
+    # the budget fails with MemoryError.
+    import concurrent.futures as cf
+    from paper_2503_18356_amd.serve import Server
+    reqs = _reqs(16, 200.0, seed=4)
+    clock = FakeClock()
+    holder = [None]
+    ex = OracleExecutor(holder, clock, batch_cost=400)
+    budget = 3 * max(footprint_bytes(r.topo.n_genes, r.topo.n_edges, r.n_sets, r.n_ic) for r in reqs)
+    with Server(hbm_budget=budget, executor=ex, clock=clock) as srv:
+        holder[0] = srv.sched
+        with cf.ThreadPoolExecutor(4) as pool:
+            futs = list(pool.map(lambda r: srv.submit(r.topo, r.seed, r.n_sets, r.n_ic), reqs))
+        too_big = srv.submit(reqs[0].topo, 1, 10**9, 10)
+        done = [f.result(timeout=120) for f in futs]
+        with pytest.raises(MemoryError):
+            too_big.result(timeout=120)
+    assert sorted(d.rid for d in done) == sorted(set(d.rid for d in done))
+    for r, d in zip(reqs, done):
+        assert (d.topo, d.seed, d.n_sets, d.n_ic) == (r.topo, r.seed, r.n_sets, r.n_ic)
+        assert d.finished >= d.admitted >= d.arrival >= 0
+        net = oracle.canonicalize(r.topo.n_genes, r.topo.src, r.topo.dst, r.topo.sign)
+        ref = oracle.steady_states(net, oracle.sample(net, r.seed, r.n_sets, r.n_ic), oracle.Opts(ss_rtol=1e-5),
+                                   n_threads=2)
+        assert np.array_equal(d.result.x, ref.x)
+    assert ex.max_used <= budget and max(ex.concurrent) >= 2
+    with pytest.raises(RuntimeError):
+        srv.submit(reqs[0].topo, 1, 10, 1)
