@@ -229,15 +229,38 @@ def cpu_oracle_multi(nets, n_pilot, target_s=12.0):
                       f"DP5(4), {threads} threads, {cw:.1f} s wall"}
 
 
-def serving_run(n_req, warm, rate, seed=5, budget=64 << 30, batch_steps=512):
+def serving_parity(reqs, rng, per_request=20):
+    """GPU results of sampled serving requests against the FP64 oracle:
+    parity_report on seeded trajectories of each request."""
+    reps = []
+    for req in reqs:
+        ids = np.sort(rng.choice(req.n_traj, min(per_request, req.n_traj), replace=False))
+        x = req.result.x.cpu().numpy()[ids]
+        reps.append(parity_report(req.topo, req.seed, req.n_sets, req.n_ic, ids, x, {"ss_rtol": 1e-5}))
+    if not reps:
+        return {}
+    return {"requests": len(reps), "n": sum(r["n"] for r in reps),
+            "max_norm_err": max(r["max_norm_err"] for r in reps),
+            "trajectories_over_1e-4": sum(r["trajectories_over_1e-4"] for r in reps),
+            "what": "a seeded 1 % of the measured requests, 20 seeded trajectories each (all of smaller "
+                    "ones), GPU FP32 vs the FP64 oracle; error = |x_gpu - x_ref| / (G/k) per component"}
+
+
+def serving_run(n_req, warm, rate, seed=5, budget=64 << 30, batch_steps=512, check_parity=True):
     from paper_2503_18356_amd.serve import GpuExecutor, Scheduler, poisson_requests
     rng = np.random.default_rng(seed)
     reqs = poisson_requests(rng, n_req + warm, rate=rate)
     ex = GpuExecutor(batch_steps=batch_steps, keep_results=False)
+    # A seeded 1 % of the measured requests keep their results for parity.
+    prng = np.random.default_rng(seed + 1)
+    ex.keep_rids = set(int(r) for r in prng.choice(np.arange(warm, n_req + warm), max(1, n_req // 100),
+                                                  replace=False))
     sched = Scheduler(ex, hbm_budget=budget)
     t0 = time.perf_counter()
     sched.run(reqs, max_seconds=900, progress=lambda m: print(m, file=sys.stderr, flush=True))
     st = sched.stats(skip=warm)
+    if check_parity:
+        st["parity"] = serving_parity([r for r in sched.done if r.rid in ex.keep_rids], prng)
     st.update({"offered_req_per_s": rate, "warmup_requests": warm, "wall_s": time.perf_counter() - t0,
                "kernel_classes": len(ex.classes), "batch_steps": batch_steps,
                "what": "Poisson arrivals of random networks (N log-uniform 2-100, E = 2.5N, "

@@ -266,6 +266,7 @@ class GpuExecutor:
         self.max_requests = max_requests
         self.device = device
         self.keep_results = keep_results
+        self.keep_rids: set[int] = set()  # results kept even without keep_results
         self.merge_slack = merge_slack
         self.streams = [torch.cuda.Stream(device=device) for _ in range(max(1, n_streams))]
         self.classes: dict[tuple, dict] = {}
@@ -398,7 +399,7 @@ class GpuExecutor:
         # Parameters go; the result tensors stay with the request unless the
         # caller only wants throughput and latency.
         req.handle["params"] = None
-        if not self.keep_results:
+        if not self.keep_results and req.rid not in self.keep_rids:
             req.result = None
 
 
