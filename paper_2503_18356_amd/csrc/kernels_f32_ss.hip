@@ -13,7 +13,7 @@ static const KernelEntry kTable[] = {
     RAC_K(12, 2), RAC_K(12, 3), RAC_K(12, 4), RAC_K(12, 6), RAC_K(12, 8), RAC_K(16, 1),
     RAC_K(16, 2), RAC_K(16, 3), RAC_K(16, 4), RAC_K(16, 6), RAC_K(16, 8), RAC_K(24, 1),
     RAC_K(24, 2), RAC_K(24, 3), RAC_K(24, 4), RAC_K(24, 6), RAC_K(32, 1), RAC_K(32, 2),
-    RAC_K(32, 3), RAC_K(7, 3), RAC_K(11, 3), RAC_K(13, 5),
+    RAC_K(32, 3), RAC_K(7, 3), RAC_K(11, 3), RAC_K(13, 5), RAC_K(6, 2), RAC_K(10, 4), RAC_K(6, 3),
 };
 
 int kernels_f32_ss(const KernelEntry** out) {

@@ -31,7 +31,7 @@ constexpr Shape kShapesF32[] = {
     {4, 1}, {4, 2}, {4, 3}, {4, 4}, {4, 6}, {4, 8}, {8, 1}, {8, 2}, {8, 3}, {8, 4}, {8, 6},
     {8, 8}, {12, 1}, {12, 2}, {12, 3}, {12, 4}, {12, 6}, {12, 8}, {16, 1}, {16, 2}, {16, 3},
     {16, 4}, {16, 6}, {16, 8}, {24, 1}, {24, 2}, {24, 3}, {24, 4}, {24, 6}, {32, 1}, {32, 2},
-    {32, 3}, {7, 3}, {11, 3}, {13, 5}};
+    {32, 3}, {7, 3}, {11, 3}, {13, 5}, {6, 2}, {10, 4}, {6, 3}};
 constexpr Shape kShapesF64[] = {
     {4, 1}, {4, 2}, {4, 3}, {4, 4}, {4, 6}, {8, 1}, {8, 2}, {8, 3}, {8, 4}, {12, 1}, {12, 2},
     {12, 3}, {16, 1}, {16, 2}, {7, 3}};
