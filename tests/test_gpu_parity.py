@@ -444,3 +444,24 @@ def test_time_series_full_size_sampled():
     err, _ = parity.compare_series(case.op, traj, xs, ref.x, case.n_ic)
     say("    max normalised error", float(err.max()))
     assert err.max() <= parity.TOL, (err.argmax(), err.max())
+
+
+@pytest.mark.parametrize("shape,N,E,seed,lanes", [((6, 2), 6, 15, 1, 4), ((6, 3), 9, 22, 1, 4),
+                                                  ((10, 4), 7, 17, 1, 2)],
+                         ids=["e6g2", "e6g3", "e10g4"])
+def test_added_shapes_every_mode(shape, N, E, seed, lanes):
+    # Each of the (6, 2), (6, 3) and (10, 4) kernels, picked by a seeded
+    # network at a pinned lane count, in steady-state mode with both methods
+    # and in time-series mode, against the oracle.
+    case = Case(inputs.erdos_renyi(N, E, seed), 90 + N, 200, 5)
+    assert case.T.shape(lanes, rp.FP32) == shape
+    for method in (rp.DP5, rp.TSIT5):
+        case.check(opts_for(rp.FP32, lanes_per_traj=lanes, method=method), label=f"shape {shape}")
+    tk = np.linspace(0.0, 50.0, 26)
+    opts = opts_for(rp.FP32, lanes_per_traj=lanes)
+    out = rp.integrate(case.T, case.dp, tk, opts)
+    torch.cuda.synchronize()
+    ref = oracle.time_series(case.net, case.op, tk, case.oracle_opts(opts), n_threads=THREADS)
+    err, _ = parity.compare_series(case.op, np.arange(case.n_traj), out.x.cpu().numpy(), ref.x, case.n_ic)
+    say("    series, max normalised error", float(err.max()))
+    assert err.max() <= parity.TOL
