@@ -570,6 +570,24 @@ def bench_uneven64(args, torch, rp, flops, inputs):
                          "what": "GPU FP32 vs the FP64 oracle on 1 % of every network (at least 200), "
                                  "seeded; error = |x_gpu - x_ref| / (G/k) per component; p99 is the "
                                  "worst network's"}
+    if not args.no_plain:
+        # The same batch with the paper's own solver (Tsitouras 5(4)), in its
+        # own output buffers.
+        o_ts = rp.Opts(precision=rp.FP32, method=rp.TSIT5)
+        outs_ts = [rp.alloc_result(p.n_sets * 10, T.n_genes, rp.FP32) for T, p in items]
+        fn_ts = lambda: rp.steady_states_batch([(T, p, o) for (T, p), o in zip(items, outs_ts)], o_ts,
+                                               stream=stream)
+        fn_ts()
+        w_ts, l_ts = timed(fn_ts, max(1, args.steps), stream, torch,
+                           before_last=lambda: [rp.fill_sentinels(o) for o in outs_ts])
+        rec["tsit5_fp32"] = {
+            "value": sum(solved(rp, o) for o in outs_ts) * max(1, args.steps) / w_ts, "unit": "solves/s",
+            "kernel_ms": float(l_ts.mean()),
+            "steps_per_solve": float(np.concatenate([o.n_acc.cpu().numpy().astype(np.int64)
+                                                     + o.n_rej.cpu().numpy() for o in outs_ts]).mean()),
+            "what": "FP32 chosen form with the Tsitouras 5(4) pair instead of Dormand-Prince, library lane "
+                    "model"}
+        del outs_ts
     return rec
 
 
