@@ -73,3 +73,24 @@ def test_tsit5_and_dp5_reach_the_same_states():
         f"{np.percentile(d.max(axis=1), 99):.2e}")
     assert flips <= 0.005 * case.n_traj
     assert np.percentile(d.max(axis=1), 99) < 1e-4
+
+
+def test_tsit5_uneven_batch():
+    # The batch call with the Tsitouras pair: each network's results equal
+    # its one-network solve at the batch's lane count, and match the
+    # oracle's Tsit5.
+    topos = inputs.uneven_batch(1005, n_networks=6, n_min=5, n_max=50)
+    cases = [Case(t, 3100 + i, 50 + 9 * i, 3) for i, t in enumerate(topos)]
+    opts = tsit5(rp.FP32)
+    say("[gpu] tsit5 batch of", [t.n_genes for t in topos])
+    outs = rp.steady_states_batch([(c.T, c.dp) for c in cases], opts)
+    torch.cuda.synchronize()
+    total = sum(c.n_traj for c in cases)
+    for c, o in zip(cases, outs):
+        single = c.gpu(tsit5(rp.FP32, lanes_per_traj=c.T.auto_lanes(rp.FP32, total)))
+        assert torch.equal(single.x, o.x), c.topo.name
+        traj = np.arange(min(c.n_traj, 60))
+        ref = oracle.steady_states(c.net, c.op, c.oracle_opts(opts), traj_ids=traj, n_threads=THREADS)
+        rep = parity.compare_steady(c.net, c.op, c.oracle_opts(opts), traj, o.x.cpu().numpy()[traj],
+                                    ref.x, c.n_ic, o.status.cpu().numpy()[traj], ref.status)
+        assert rep.ok(), (c.topo.name, rep)
