@@ -48,6 +48,25 @@ def test_noalloc_matches_steady_states_twice(prec):
         assert int((out.status < 0).sum()) == 0
 
 
+def test_noalloc_with_the_four_wave_spilling_shape():
+    # The (10, 4) steady-state kernel, asked for four waves per SIMD, keeps a
+    # few registers in per-lane scratch: the entry point without allocation
+    # still matches rac_steady_states on it, twice.
+    T = rp.Topology.from_inputs(inputs.erdos_renyi(7, 17, 1))
+    assert T.shape(2, rp.FP32) == (10, 4)
+    opts = rp.Opts(precision=rp.FP32, ss_rtol=1e-5, lanes_per_traj=2)
+    print("[gpu] noalloc shape (10, 4)", flush=True)
+    for n_sets, n_ic in ((2000, 10), (300, 2)):
+        dp = rp.sample_params(T, 55 + n_sets, n_sets, n_ic).to_device()
+        ref = rp.steady_states(T, dp, opts)
+        torch.cuda.synchronize()
+        out = _filled(n_sets * n_ic, T.n_genes, rp.FP32)
+        rp.steady_states_noalloc(T, dp, opts, out)
+        torch.cuda.synchronize()
+        _same(ref, out)
+        assert int((out.status < 0).sum()) == 0
+
+
 def test_noalloc_needs_a_prepared_lane_plan():
     T = rp.Topology.from_inputs(inputs.dense_core(1004))
     dp = rp.sample_params(T, 5, 10, 2).to_device()
