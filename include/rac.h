@@ -298,7 +298,10 @@ rac_status rac_steady_states(const rac_topology* topo, const rac_params_view* de
  * overlap on one GPU (concurrent streams or threads) share that scratch and
  * race: order them on one stream.  The network's lane plan for the lane count
  * the options select must already be on the current device, which any
- * earlier rac_steady_states call with the same options leaves there.
+ * earlier rac_steady_states call with the same options leaves there.  Kernel
+ * shapes that keep a few registers in per-lane scratch (the four-wave
+ * (10, 4) shape) use the HIP runtime's private segment for them, which the
+ * runtime provides at dispatch; this call allocates nothing itself.
  * EINVAL as rac_steady_states, and when the lane plan is not on the device;
  * EUNSUPPORTED as rac_steady_states; EDEVICE if the scratch address cannot be
  * found. */
