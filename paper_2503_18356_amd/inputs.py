@@ -170,3 +170,52 @@ def serving_request(rng, n_lo: int = 2, n_hi: int = 100, p_lo: int = 100, p_hi: 
     p = max(p_lo, min(p_hi, log_uniform_int(rng, p_lo, p_hi)))
     n_ic = int(rng.integers(ic_lo, ic_hi + 1))
     return topo, p, n_ic
+
+
+# Edge-type codes of the topology text layout: 1 activation, 2 inhibition.
+_TOPO_SIGN = {1: 1, 2: -1}
+
+
+def parse_topo(text: str, name: str = "") -> tuple[Topology, list[str]]:
+    """A network from a topology text: one edge per line as whitespace-separated
+    "source target type", type 1 = activation and 2 = inhibition (the paper
+    takes networks as a topology file, Sec. 2.1.1, without stating its layout;
+    this is the layout RACIPE tools commonly use).  A first line whose type
+    field is not an integer is a header and is skipped, as are blank lines and
+    lines starting with '#'.  Genes are numbered in order of first appearance
+    (source before target, line by line); the names come back in that order.
+    Raises ValueError on a line without three fields or with another type code.
+    Duplicate edges pass through: the library's topology call rejects them."""
+    names: dict[str, int] = {}
+    edges = []
+    first = True
+    for ln, raw in enumerate(text.splitlines(), 1):
+        line = raw.strip()
+        if not line or line.startswith("#"):
+            continue
+        parts = line.split()
+        if len(parts) != 3:
+            raise ValueError(f"line {ln}: expected 'source target type', got {raw!r}")
+        try:
+            code = int(parts[2])
+        except ValueError:
+            if first:
+                first = False
+                continue
+            raise ValueError(f"line {ln}: edge type {parts[2]!r} is not an integer") from None
+        first = False
+        if code not in _TOPO_SIGN:
+            raise ValueError(f"line {ln}: edge type {code} (1 = activation, 2 = inhibition)")
+        s = names.setdefault(parts[0], len(names))
+        d = names.setdefault(parts[1], len(names))
+        edges.append((s, d, _TOPO_SIGN[code]))
+    if not names:
+        raise ValueError("topology text holds no edges")
+    return _topo(len(names), edges, name), list(names)
+
+
+def read_topo(path: str) -> tuple[Topology, list[str]]:
+    """parse_topo() on a file; the network is named after the file."""
+    import os
+    with open(path) as f:
+        return parse_topo(f.read(), os.path.splitext(os.path.basename(path))[0])
