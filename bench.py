@@ -70,6 +70,50 @@ def measured_traffic(workload: str):
     return None
 
 
+def profile_counter(workload: str, counter: str):
+    """The chosen-form (first) value of a counter in the committed rocprofv3
+    summary of a workload, or None when the kernel sources changed since the
+    counters were taken."""
+    import glob
+    import re
+    want = kernel_source_hash()
+    for f in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        txt = open(f).read()
+        m = re.search(r"`kernel_source_hash: ([0-9a-f]+)` `workload: ([\w.]+)`", txt)
+        if m and m.group(1) == want and m.group(2) == workload:
+            v = re.search(r"\| " + re.escape(counter) + r" \| ([0-9.eE+-]+) \|", txt)
+            return float(v.group(1)) if v else None
+    return None
+
+
+_CEILINGS = {}
+
+
+def ceilings(rp, args):
+    """VALU ceilings measured once per run on this device (None with --no-ceilings)."""
+    if args.no_ceilings:
+        return None
+    if "c" not in _CEILINGS:
+        _CEILINGS["c"] = rp.valu_ceilings()
+    return _CEILINGS["c"]
+
+
+def transcendental_rate(rp, args, workload: str, kernel_ms: float):
+    """Transcendental throughput of the FP32 kernels: the transcendental
+    instructions of the committed counter run (SQ_INSTS_VALU_TRANS_F32, per
+    launch or batch call) x 64 lanes over this run's kernel time, against the
+    sustained v_exp_f32 rate measured on this device (v_exp, v_log and v_rcp
+    issue alike)."""
+    n = profile_counter(workload, "SQ_INSTS_VALU_TRANS_F32")
+    c = ceilings(rp, args)
+    if n is None or c is None:
+        return None
+    ach = n * 64 / (kernel_ms * 1e-3)
+    return {"achieved_tops": ach / 1e12, "ceiling_tops": c["v_exp_f32"] / 1e12, "frac": ach / c["v_exp_f32"],
+            "what": "transcendental lane operations per second (counter run's instruction count x 64 "
+                    "lanes, this run's kernel time) against the measured v_exp_f32 rate"}
+
+
 def timed(fn, steps, stream, torch, before_last=None):
     """Run fn() `steps` times between synchronisations; HIP events on the
     launch stream bracket each call.  before_last() runs ahead of the last
@@ -187,15 +231,31 @@ def parity_report(topo, seed, n_sets, n_ic, ids, x_rows, opts_kw, t_out=None):
     d = np.abs(x - ref.x)
     err = d / gk
     rel = d / np.maximum(np.abs(ref.x), 1e-12)
+    # The step control is relative only where |x| >= atol / rtol (1e-9 / 1e-6
+    # by default); below that it bounds the absolute error, and the plain
+    # relative error of a level near zero says little.
+    floor = opts_kw.get("atol", 1e-9) / opts_kw.get("rtol", 1e-6)
+    rel_c = np.where(np.abs(ref.x) >= floor, rel, 0.0)
     per_traj = err.reshape(len(ids), -1).max(axis=1)
     rec = {"n": int(len(ids)), "max_norm_err": float(err.max()),
            "p99_norm_err": float(np.percentile(err, 99)),
            "rel_p50": float(np.percentile(rel, 50)), "rel_p99": float(np.percentile(rel, 99)),
+           "rel_max": float(rel.max()), "rel_max_where_x_ge_atol_over_rtol": float(rel_c.max()),
            "trajectories_over_1e-4": int((per_traj > 1e-4).sum()),
            "what": "GPU FP32 vs the FP64 oracle on a seeded sample; error = |x_gpu - x_ref| / (G/k) "
                    "per component"}
     if t_out is not None:
-        rec["max_norm_err_every_10th_time"] = [float(v) for v in err.max(axis=(0, 2))[::10]]
+        # Per output time over the sample and the genes (3 significant digits).
+        r3 = lambda a: [float(f"{v:.3g}") for v in a]
+        rec["per_time"] = {"t": r3(t_out), "max_norm_err": r3(err.max(axis=(0, 2))),
+                           "max_rel_err": r3(rel.max(axis=(0, 2))),
+                           "rel_p99": r3(np.percentile(rel, 99, axis=(0, 2))),
+                           "max_rel_err_where_x_ge_atol_over_rtol": r3(rel_c.max(axis=(0, 2))),
+                           "what": "at every output time: the largest normalised error, the "
+                                   "largest plain relative error |x_gpu - x_ref| / max(|x_ref|, 1e-12), "
+                                   "its 99th percentile over the sample's components, and the largest "
+                                   "over components with |x_ref| >= atol / rtol, where the step control "
+                                   "is relative (below it the control bounds the absolute error)"}
     return rec
 
 
@@ -326,7 +386,7 @@ def bench_er10(args, torch, rp, flops, inputs):
     if not args.no_ceilings:
         # Secondary ceilings measured on this device (unpacked FP32 FMA, the
         # transcendentals, FP64 FMA), beside the published peaks.
-        c = rp.valu_ceilings()
+        c = ceilings(rp, args)
         rec["measured_ceilings"] = {
             "fp32_fma_tflops": 2 * c["fp32_fma"] / 1e12,
             "v_exp_f32_tops": c["v_exp_f32"] / 1e12, "v_log_f32_tops": c["v_log_f32"] / 1e12,
@@ -335,6 +395,9 @@ def bench_er10(args, torch, rp, flops, inputs):
                     "FP32), all lanes of the device; fp32_fma takes its operands from registers "
                     "(v_fma_f32, as the solver does)"}
         rec["roofline"]["frac_of_measured_fp32_fma"] = achieved / (2 * c["fp32_fma"])
+        if default_cfg:
+            rec["roofline"]["transcendental"] = transcendental_rate(rp, args, "er10_1e6_fp32",
+                                                                    float(lat.mean()))
     if not args.no_plain:
         o64 = rp.Opts(precision=rp.FP64, ss_rtol=1e-5, lanes_per_traj=args.lanes)
         out64 = rp.alloc_result(n_traj, T.n_genes, rp.FP64, device=dev)
@@ -528,6 +591,8 @@ def bench_uneven64(args, torch, rp, flops, inputs):
         "steps_per_solve": float(np.concatenate(steps_all).mean()),
         "device_sampling_s": t_sample,
     })
+    if default_cfg:
+        rec["roofline"]["transcendental"] = transcendental_rate(rp, args, "uneven64_fp32", launch_ms)
     if tune_rec is not None:
         tune_rec["picked_over_default"] = v32 / tune_rec["default_value"]
         rec["autotune"] = tune_rec
@@ -565,6 +630,8 @@ def bench_uneven64(args, torch, rp, flops, inputs):
         rec["parity"] = {"n": sum(r["n"] for r in reps),
                          "max_norm_err": max(r["max_norm_err"] for r in reps),
                          "p99_norm_err": max(r["p99_norm_err"] for r in reps),
+                         "rel_max_where_x_ge_atol_over_rtol": max(r["rel_max_where_x_ge_atol_over_rtol"]
+                                                                  for r in reps),
                          "trajectories_over_1e-4": sum(r["trajectories_over_1e-4"] for r in reps),
                          "networks": len(reps),
                          "what": "GPU FP32 vs the FP64 oracle on 1 % of every network (at least 200), "
@@ -638,6 +705,7 @@ def bench_core22ts(args, torch, rp, flops, inputs):
                                "credited_fp64_tflops": fl64 / (l64.mean() * 1e-3) / 1e12,
                                "frac_of_fp64_peak": fl64 / (l64.mean() * 1e-3) / PEAK_FP64},
                 "speedup_fp32_vs_fp64": v32 / v64})
+    rec["roofline"]["transcendental"] = transcendental_rate(rp, args, "core22ts_fp32", float(lat.mean()))
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_oracle(topo, 2004, P, n_ic, 1000, {"ss_rtol": 1e-5}, t_out=tk,
                                          target_s=args.cpu_seconds)
