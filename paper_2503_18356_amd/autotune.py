@@ -65,8 +65,15 @@ class Autotuner:
         self.path = cache_path
         self.cache = {}
         if os.path.exists(cache_path):
-            with open(cache_path) as f:
-                self.cache = json.load(f)
+            # A cache that cannot be read (cut short, edited by hand) is
+            # dropped and measured again rather than failing the caller.
+            try:
+                with open(cache_path) as f:
+                    c = json.load(f)
+                if isinstance(c, dict):
+                    self.cache = c
+            except (OSError, ValueError):
+                self.cache = {}
 
     def _key(self, topo, precision: int) -> str:
         return f"{arch()}|{'fp32' if precision == rp.FP32 else 'fp64'}|{bucket(topo)}"

@@ -56,3 +56,20 @@ def test_refine_batch_keeps_only_switches_that_pay():
     # A group whose tuned knobs equal the current ones is not tried again.
     knobs2, log2 = Autotuner.refine_batch(run, default, default, [[0, 1]])
     assert knobs2 == default and len(log2) == 1
+
+
+def test_autotune_cache_that_cannot_be_read_is_dropped(tmp_path):
+    # A cut-short or hand-edited cache file starts an empty cache (measured
+    # again on use) instead of failing; a readable one is kept.
+    import json
+    from paper_2503_18356_amd.autotune import Autotuner
+    bad = tmp_path / "cut.json"
+    bad.write_text('{"gfx950|fp32|N16_E32_D4": {"lanes": 4,')
+    assert Autotuner(str(bad)).cache == {}
+    wrong = tmp_path / "list.json"
+    wrong.write_text("[1, 2]")
+    assert Autotuner(str(wrong)).cache == {}
+    good = tmp_path / "good.json"
+    entry = {"k": {"lanes": 4, "refill_min": 2, "solves_per_s": 1.0}}
+    good.write_text(json.dumps(entry))
+    assert Autotuner(str(good)).cache == entry
