@@ -53,7 +53,25 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     tmp = LIB + ".tmp"
     _run(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, LIB)
+    build_c_demo()
     return LIB
+
+
+C_DEMO_SRC = os.path.join(ROOT, "tests", "c_abi_demo.c")
+C_DEMO = os.path.join(ROOT, "tests", "c_abi_demo")
+
+
+def build_c_demo() -> str:
+    """The plain C caller of the ABI that the tests run: C99 with gcc, the HIP
+    runtime's C API and librac.so, found next to it at run time."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    tmp = C_DEMO + ".tmp"
+    _run(["gcc", "-std=c99", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(rocm, "include"),
+          "-I", INCLUDE, C_DEMO_SRC, "-L", HERE, "-lrac", "-L", os.path.join(rocm, "lib"), "-lamdhip64",
+          "-Wl,-rpath,$ORIGIN/../paper_2503_18356_amd", "-Wl,-rpath," + os.path.join(rocm, "lib"),
+          "-o", tmp])
+    os.replace(tmp, C_DEMO)
+    return C_DEMO
 
 
 if __name__ == "__main__":

@@ -255,3 +255,14 @@ def test_postprocessing_rejects_bad_arguments_before_enqueue():
     v = p.view()
     assert L.rac_normalize(t.handle, C.byref(v), 0, 1, fake, fake, s) == rp.EINVAL
     assert L.rac_normalize(t.handle, C.byref(v), 2, 1, None, fake, s) == rp.EINVAL
+
+
+def test_plain_c_caller_links_against_the_library():
+    # tests/c_abi_demo.c is C99 that calls the ABI with no Python and no C++;
+    # built with the library, it loads librac.so and, without arguments,
+    # prints its usage before any device call.
+    import subprocess
+    from paper_2503_18356_amd import build
+    exe = build.C_DEMO if os.path.exists(build.C_DEMO) else build.build_c_demo()
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 1 and "usage:" in r.stderr, (r.returncode, r.stderr)
