@@ -274,19 +274,24 @@ def cpu_oracle_multi(nets, n_pilot, target_s=12.0):
     o = oracle.Opts(ss_rtol=1e-5)
     rng = np.random.default_rng(0)
 
-    def run(n):
+    def run(n, n_threads=threads):
         ids = np.sort(rng.choice(int(starts[-1]), min(n, int(starts[-1])), replace=False))
         c0 = time.perf_counter()
         for i, (net, op, _) in enumerate(prepared):
             sel = ids[(ids >= starts[i]) & (ids < starts[i + 1])] - starts[i]
             if sel.size:
-                oracle.steady_states(net, op, o, traj_ids=sel, n_threads=threads)
+                oracle.steady_states(net, op, o, traj_ids=sel, n_threads=n_threads)
         return ids.size, time.perf_counter() - c0
 
     n1, cw = grow(run, n_pilot, int(starts[-1]), target_s)
-    return {"value": n1 / cw, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n1} seeded random trajectories across the workload's networks, FP64 "
-                      f"DP5(4), {threads} threads, {cw:.1f} s wall"}
+    rec = {"value": n1 / cw, "unit": "solves/s", "cores": threads, "kind": "oracle",
+           "sample": f"{n1} seeded random trajectories across the workload's networks, FP64 "
+                     f"DP5(4), {threads} threads, {cw:.1f} s wall",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    k1, w1 = run(max(1, n1 // (4 * threads)), 1)
+    rec["single_thread"] = {"value": k1 / w1, "unit": "solves/s",
+                            "sample": f"{k1} seeded random trajectories, {w1:.1f} s wall"}
+    return rec
 
 
 def serving_parity(reqs, rng, per_request=20):
